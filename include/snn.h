@@ -1,0 +1,153 @@
+/*
+ * snn.h - C ABI of the MI355X (gfx950) Sinnamon library.
+ *
+ * Sinnamon (Bruch, Nardini, Ingber, Liberty; arXiv 2301.10622) answers
+ * approximate top-k maximum inner product queries over a streaming collection
+ * of sparse real-valued vectors. The problem statement (Eq. 1-2 and the online
+ * setting of Section 1) fixes the three calls this library is built around:
+ * insert(id, x), delete(id) and search(q, k).
+ *
+ * Conventions shared by every call:
+ *   - Vectors are sparse: `nnz` coordinates in [0, dim) with float32 values.
+ *     Coordinates need not be sorted. A value of exactly 0 is not a
+ *     coordinate (nz() of Alg. 1 / Alg. 5) and is dropped. Duplicate
+ *     coordinates, coordinates >= dim and non-finite values are rejected.
+ *   - Ids are caller-chosen uint32 in [0, 0xFFFFFFFE]. 0xFFFFFFFF is reserved.
+ *   - Host pointers are read before the call returns; the caller keeps
+ *     ownership of every buffer it passes. The index owns all device memory it
+ *     allocates and frees it in snn_destroy.
+ *   - "_dev" entry points take device pointers (hipMalloc'd or a PyTorch CUDA
+ *     tensor's data pointer on ROCm) and a hipStream_t (as void*, NULL = the
+ *     stream given at creation). They enqueue work and return; results are
+ *     valid once that stream has been synchronised.
+ *   - Every call returns a status. On an error the index is unchanged and
+ *     snn_last_error() describes the problem. No C++ exception crosses the ABI.
+ *   - One index is used by one host thread at a time.
+ *
+ * Search results are sorted by Sinnamon score descending, ties by the lower
+ * external id (the selection of Alg. 3 with k' = k, Alg. 7 reduced), and hold
+ * min(k, live documents) entries. Documents that share no coordinate with the
+ * query score exactly 0 and still take part in the ranking (Section 3).
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SNN_OK = 0,
+  SNN_E_INVALID = -1,   /* bad argument or malformed vector */
+  SNN_E_EXISTS = -2,    /* insert of an id that is already live */
+  SNN_E_NOT_FOUND = -3, /* delete of an id that is not live */
+  SNN_E_FULL = -4,      /* no free slot left (capacity reached) */
+  SNN_E_NOMEM = -5,     /* device or host allocation failed */
+  SNN_E_BUSY = -6,      /* serving admission: over the device memory budget */
+  SNN_E_DEVICE = -7     /* a HIP call failed */
+} snn_status;
+
+/* Sketch configuration: Sinnamon_(2m, h) of Alg. 5/6.
+ *   dim       n, the dimensionality of the vectors
+ *   m         buckets per half of the sketch (U and L each hold m rows)
+ *   h         number of random mappings pi_o : [n] -> [m], 1..4
+ *   hash_seed the mappings are pi_o(j) = mix64(mix64(hash_seed + o) XOR j) mod m
+ *             with mix64 the SplitMix64 output function (Steele, Lea, Flood
+ *             2014); the paper leaves the mappings unspecified
+ *   capacity  maximum number of live documents (document slots); rounded up
+ *             to a multiple of 16384 internally
+ *   flags     reserved, must be 0 */
+typedef struct {
+  uint32_t dim;
+  uint32_t m;
+  uint32_t h;
+  uint32_t capacity;
+  uint64_t hash_seed;
+  uint32_t flags;
+  uint32_t reserved;
+} snn_config;
+
+typedef struct snn_index snn_index;
+
+/* Create an empty index. `hip_stream` (a hipStream_t, may be NULL for the
+ * default stream) is where the index's own work is enqueued. Device memory for
+ * the posting bitmaps (dim x capacity bits), the sketch matrix (2m x capacity
+ * float32, the row-major layout of Section 4.1 "Notes on Implementation") and
+ * the slot maps is allocated here. Errors: SNN_E_INVALID (dim or m is 0, h not
+ * in 1..4, capacity 0 or above 2^31), SNN_E_NOMEM, SNN_E_DEVICE. */
+snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_index **out);
+void snn_destroy(snn_index *ix);
+
+/* Insert one vector under `id` (Alg. 5): its id goes onto the inverted list of
+ * every non-zero coordinate and its sketch (u = bucket max, l = bucket min;
+ * buckets no coordinate maps to are written 0) into a free column of U and L.
+ * A column freed by a delete is reused first (Section 4.3). Host pointers.
+ * Errors: SNN_E_INVALID, SNN_E_EXISTS, SNN_E_FULL, SNN_E_DEVICE. */
+snn_status snn_insert(snn_index *ix, uint32_t id, uint32_t nnz, const uint32_t *coords, const float *vals);
+
+/* Insert `n` vectors in CSR form: vector r is coords/vals[indptr[r] ..
+ * indptr[r+1]). Host pointers. All-or-nothing: on error nothing is inserted. */
+snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t *ids, const uint64_t *indptr,
+                            const uint32_t *coords, const float *vals);
+
+/* Delete `id` (Section 4.3): its slot leaves every inverted list it is on and
+ * the live set; the sketch column is left as it is and the slot is reused by a
+ * later insert. Errors: SNN_E_NOT_FOUND, SNN_E_DEVICE. */
+snn_status snn_delete(snn_index *ix, uint32_t id);
+snn_status snn_delete_batch(snn_index *ix, uint32_t n, const uint32_t *ids);
+
+/* Search one query (Alg. 6 scoring with T = infinity, then Alg. 3 / Alg. 7 with
+ * k' = k). Writes up to k results to out_ids / out_scores (caller-allocated, k
+ * entries each) and the result count to *out_count. Host pointers; returns
+ * after the results are on the host. Errors: SNN_E_INVALID (k = 0 or a
+ * malformed query), SNN_E_NOMEM, SNN_E_DEVICE. */
+snn_status snn_search(snn_index *ix, uint32_t nnz, const uint32_t *coords, const float *vals, uint32_t k,
+                      uint32_t *out_ids, float *out_scores, uint32_t *out_count);
+
+/* Search nq queries given in CSR form (query r owns entries indptr[r] ..
+ * indptr[r+1]). Outputs are nq x k row-major plus nq counts. Host pointers. */
+snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                            const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
+                            uint32_t *out_counts);
+
+/* Search modes for the _dev batch search. */
+typedef enum {
+  SNN_MODE_PLAIN = 0,     /* one launch per query, tiles of one query at a time */
+  SNN_MODE_BATCHED = 1,   /* one persistent launch for the whole batch (HIP graph) */
+  SNN_MODE_LEARNED = 2    /* batched, with the learned k-th-score pre-filter */
+} snn_mode;
+
+/* Device-pointer batch search. indptr (nq + 1 uint64), coords, vals, and the
+ * outputs out_ids (nq x k uint32), out_scores (nq x k float32), out_counts (nq
+ * uint32) live in device memory. Enqueued on `stream` (NULL: the index
+ * stream); the call does not wait for completion except in
+ * SNN_MODE_LEARNED, which reads the fallback flags back on the host and
+ * re-runs the queries that need the plain path. Malformed queries produce a
+ * count of 0 and set the bit in the status returned by snn_last_batch_status.
+ * Errors: SNN_E_INVALID (k = 0, nq = 0, mode unknown, no trained filter for
+ * SNN_MODE_LEARNED), SNN_E_NOMEM, SNN_E_DEVICE. */
+snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
+                                float *out_scores, uint32_t *out_counts, void *stream);
+
+/* Number of queries of the last snn_search_batch_dev call that were malformed
+ * (needs the stream synchronised), and, for SNN_MODE_LEARNED, how many fell
+ * back to the plain path. */
+snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks);
+
+/* Read back state for tests: the bucket table pi_o(j) as h x dim uint32
+ * (row-major), and the stored sketch column (m floats each for U and L) of a
+ * live id. Host pointers. */
+snn_status snn_bucket_table(snn_index *ix, uint32_t *out);
+snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l);
+
+size_t snn_live_count(const snn_index *ix);
+const char *snn_last_error(const snn_index *ix); /* never NULL */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SNN_H */

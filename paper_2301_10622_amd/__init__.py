@@ -1,0 +1,221 @@
+"""Python binding of libsnn.so, the MI355X (gfx950) Sinnamon library.
+
+Argument marshalling only: every step of insert, delete and search runs in the
+library's HIP kernels. PyTorch provides device memory and streams for the
+device-pointer entry points. The binding fails loudly when the library is not
+built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+try:  # load torch first so the library shares torch's HIP runtime in this process
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsnn.so")
+
+SNN_OK = 0
+STATUS = {0: "SNN_OK", -1: "SNN_E_INVALID", -2: "SNN_E_EXISTS", -3: "SNN_E_NOT_FOUND", -4: "SNN_E_FULL",
+          -5: "SNN_E_NOMEM", -6: "SNN_E_BUSY", -7: "SNN_E_DEVICE"}
+MODE_PLAIN, MODE_BATCHED, MODE_LEARNED = 0, 1, 2
+
+# every symbol include/snn.h declares (checked by the test suite)
+EXPORTS = [
+    "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
+    "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
+    "snn_read_sketch", "snn_live_count", "snn_last_error",
+]
+
+
+class SnnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_uint32), ("m", ctypes.c_uint32), ("h", ctypes.c_uint32),
+                ("capacity", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libsnn.so is not built: run __graft_entry__.build() (hipcc for gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, u32, u64, i32, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t
+        L.snn_create.argtypes = [ctypes.POINTER(Config), P, ctypes.POINTER(P)]
+        L.snn_destroy.argtypes = [P]
+        L.snn_destroy.restype = None
+        L.snn_insert.argtypes = [P, u32, u32, P, P]
+        L.snn_insert_batch.argtypes = [P, u32, P, P, P, P]
+        L.snn_delete.argtypes = [P, u32]
+        L.snn_delete_batch.argtypes = [P, u32, P]
+        L.snn_search.argtypes = [P, u32, P, P, u32, P, P, P]
+        L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
+        L.snn_search_batch_dev.argtypes = [P, u32, P, P, P, u32, u32, P, P, P, P]
+        L.snn_last_batch_status.argtypes = [P, P, P]
+        L.snn_bucket_table.argtypes = [P, P]
+        L.snn_read_sketch.argtypes = [P, u32, P, P]
+        L.snn_live_count.argtypes = [P]
+        L.snn_live_count.restype = sz
+        L.snn_last_error.argtypes = [P]
+        L.snn_last_error.restype = ctypes.c_char_p
+        for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
+                     "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
+                     "snn_read_sketch"):
+            getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _tp(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Index:
+    """A device-resident Sinnamon index (owns its device memory)."""
+
+    def __init__(self, dim: int, m: int, h: int = 1, capacity: int = 1 << 16, hash_seed: int = 0, stream=None):
+        L = lib()
+        self._cfg = Config(dim, m, h, capacity, hash_seed, 0, 0)
+        self.dim, self.m, self.h = dim, m, h
+        h_ptr = ctypes.c_void_p()
+        if stream is None and torch is not None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        st = L.snn_create(ctypes.byref(self._cfg), _stream_handle(stream) if stream is not None else None,
+                          ctypes.byref(h_ptr))
+        if st != SNN_OK:
+            raise SnnError(st, "snn_create failed")
+        self._h = h_ptr
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().snn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != SNN_OK:
+            raise SnnError(st, lib().snn_last_error(self._h).decode())
+
+    # ------------------------------------------------------------------ updates
+    def insert(self, id: int, coords, vals):
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        self._check(lib().snn_insert(self._h, int(id), len(c), _p(c), _p(v)))
+
+    def insert_batch(self, ids, indptr, coords, vals):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        self._check(lib().snn_insert_batch(self._h, len(ids), _p(ids), _p(ip), _p(c), _p(v)))
+
+    def delete(self, id: int):
+        self._check(lib().snn_delete(self._h, int(id)))
+
+    def delete_batch(self, ids):
+        ids = np.ascontiguousarray(ids, dtype=np.uint32)
+        self._check(lib().snn_delete_batch(self._h, len(ids), _p(ids)))
+
+    @property
+    def live_count(self) -> int:
+        return int(lib().snn_live_count(self._h))
+
+    # ------------------------------------------------------------------- search
+    def search(self, coords, vals, k: int) -> Tuple[np.ndarray, np.ndarray]:
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        ids = np.zeros(k, np.uint32)
+        sc = np.zeros(k, np.float32)
+        cnt = np.zeros(1, np.uint32)
+        self._check(lib().snn_search(self._h, len(c), _p(c), _p(v), k, _p(ids), _p(sc), _p(cnt)))
+        return ids[: cnt[0]], sc[: cnt[0]]
+
+    def search_batch(self, indptr, coords, vals, k: int):
+        ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        nq = len(ip) - 1
+        ids = np.zeros((nq, k), np.uint32)
+        sc = np.zeros((nq, k), np.float32)
+        cnt = np.zeros(nq, np.uint32)
+        self._check(lib().snn_search_batch(self._h, nq, _p(ip), _p(c), _p(v), k, _p(ids), _p(sc), _p(cnt)))
+        return ids, sc, cnt
+
+    def search_batch_dev(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, out=None, stream=None):
+        """Device tensors in, device tensors out (ids, scores, counts); enqueued on `stream`."""
+        nq = indptr.numel() - 1
+        dev = indptr.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev),
+                   torch.empty(nq, dtype=torch.int32, device=dev))
+        ids, sc, cnt = out
+        assert indptr.dtype == torch.int64 and coords.dtype == torch.int32 and vals.dtype == torch.float32
+        assert indptr.is_contiguous() and coords.is_contiguous() and vals.is_contiguous()
+        assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
+        self._check(lib().snn_search_batch_dev(self._h, nq, _tp(indptr), _tp(coords), _tp(vals), k, mode,
+                                               _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
+        return ids, sc, cnt
+
+    def last_batch_status(self):
+        inv = ctypes.c_uint32()
+        fb = ctypes.c_uint32()
+        self._check(lib().snn_last_batch_status(self._h, ctypes.byref(inv), ctypes.byref(fb)))
+        return int(inv.value), int(fb.value)
+
+    # ------------------------------------------------------------- inspection
+    def bucket_table(self) -> np.ndarray:
+        out = np.zeros((self.h, self.dim), np.uint32)
+        self._check(lib().snn_bucket_table(self._h, _p(out)))
+        return out
+
+    def read_sketch(self, id: int):
+        u = np.zeros(self.m, np.float32)
+        l = np.zeros(self.m, np.float32)
+        self._check(lib().snn_read_sketch(self._h, int(id), _p(u), _p(l)))
+        return u, l
+
+
+def load_docs(index: Index, docs, ids: Optional[np.ndarray] = None, chunk: int = 1 << 18):
+    """Insert a CSR batch of documents (ids default to 0..rows-1)."""
+    n = docs.rows
+    if ids is None:
+        ids = np.arange(n, dtype=np.uint32)
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        ip = docs.indptr[a:b + 1] - docs.indptr[a]
+        c = docs.coords[docs.indptr[a]:docs.indptr[b]]
+        v = docs.vals[docs.indptr[a]:docs.indptr[b]]
+        index.insert_batch(ids[a:b], ip, c, v)

@@ -1,0 +1,230 @@
+// Index-update kernels (insert: Alg. 5; delete: Section 4.3) and query
+// preparation (the first steps of Alg. 6).
+#include "snn_device.h"
+
+namespace snn {
+
+// ---------------------------------------------------------------------------
+// Insert (Alg. 5). One wavefront per document.
+//   1. every (coordinate, mapping) pair folds its value into its bucket's
+//      running max and min, kept in LDS as order-preserving integer keys so
+//      plain integer atomics give the exact float max/min in any order;
+//   2. the column `slot` of U and L is written whole (buckets no coordinate
+//      maps to get 0), so a reused column holds no trace of its last owner;
+//   3. the slot's bit is set in the posting bitmap of every coordinate, in the
+//      live bitmap, and slot2id records the external id.
+// The caller guarantees the slot's old postings were cleared before (delete).
+// ---------------------------------------------------------------------------
+constexpr int kInsertMaxM = 1024;
+
+__global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const uint32_t *__restrict__ slots,
+                                               const uint32_t *__restrict__ ids,
+                                               const uint64_t *__restrict__ indptr,
+                                               const uint32_t *__restrict__ coords,
+                                               const float *__restrict__ vals) {
+  __shared__ uint32_t umax[kInsertMaxM];
+  __shared__ uint32_t umin[kInsertMaxM];
+  const uint32_t d = blockIdx.x;
+  if (d >= n) return;
+  const int lane = threadIdx.x;
+  const uint32_t m = ix.m, h = ix.h;
+  for (uint32_t b = lane; b < m; b += 64) {
+    umax[b] = 0u;           // below every finite key
+    umin[b] = 0xFFFFFFFFu;  // above every finite key
+  }
+  __syncthreads();
+  const uint64_t e0 = indptr[d], e1 = indptr[d + 1];
+  const uint32_t slot = slots[d];
+  const uint64_t bit = 1ull << (slot & 63u);
+  const size_t word = slot >> 6;
+  for (uint64_t e = e0 + lane; e < e1; e += 64) {
+    const uint32_t j = coords[e];
+    const float v = vals[e];
+    if (v == 0.0f) continue;  // not in nz(x)
+    const uint32_t key = ord_key(v);
+    for (uint32_t o = 0; o < h; ++o) {
+      const uint32_t b = ix.bucket[(size_t)o * ix.dim + j];
+      atomicMax(&umax[b], key);
+      atomicMin(&umin[b], key);
+    }
+    atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + word], (unsigned long long)bit);
+  }
+  __syncthreads();
+  for (uint32_t b = lane; b < m; b += 64) {
+    const uint32_t a = umax[b], c = umin[b];
+    ix.U[(size_t)b * ix.cap + slot] = a ? key_value(a) : 0.0f;
+    ix.L[(size_t)b * ix.cap + slot] = (c != 0xFFFFFFFFu) ? key_value(c) : 0.0f;
+  }
+  if (lane == 0) {
+    ix.slot2id[slot] = ids[d];
+    atomicOr((unsigned long long *)&ix.live[word], (unsigned long long)bit);
+  }
+}
+
+hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
+                         const uint64_t *indptr, const uint32_t *coords, const float *vals, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (ix.m > (uint32_t)kInsertMaxM) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_insert, dim3(n), dim3(64), 0, s, ix, n, slots, ids, indptr, coords, vals);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Delete (Section 4.3): clear the slot's bit in the posting bitmap of each of
+// its coordinates and/or in the live bitmap. The sketch column stays as is.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_delete(DevIndex ix, uint32_t n, const uint32_t *__restrict__ slots,
+                                               const uint64_t *__restrict__ indptr,
+                                               const uint32_t *__restrict__ coords, int clear_bits,
+                                               int clear_live) {
+  const uint32_t d = blockIdx.x;
+  if (d >= n) return;
+  const uint32_t slot = slots[d];
+  const uint64_t mask = ~(1ull << (slot & 63u));
+  const size_t word = slot >> 6;
+  if (clear_bits)
+    for (uint64_t e = indptr[d] + threadIdx.x; e < indptr[d + 1]; e += 64)
+      atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + word], (unsigned long long)mask);
+  if (clear_live && threadIdx.x == 0) atomicAnd((unsigned long long *)&ix.live[word], (unsigned long long)mask);
+}
+
+hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,
+                         const uint32_t *coords, int clear_bits, int clear_live, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_delete, dim3(n), dim3(64), 0, s, ix, n, slots, indptr, coords, clear_bits, clear_live);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks), dim3(256), 0, s, p, value, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Query preparation (Alg. 6, first steps). One workgroup per query:
+//   drop zero values (nz), reject coordinates >= dim, non-finite values and
+//   duplicate coordinates, sort by |q_j| descending with ties to the lower j
+//   (the order Alg. 6 walks the coordinates in), and look up the h buckets
+//   K = {pi_o(j)} of every coordinate.
+// Sort keys are 64-bit: high word ~|q|bits (ascending = |q| descending), low
+// word (j << 1) | sign, so equal magnitudes fall back to the lower coordinate.
+// ---------------------------------------------------------------------------
+__device__ inline void bitonic_sort_u64_asc(uint64_t *s, int n) {
+  for (int size = 2; size <= n; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint64_t a = s[lo], b = s[hi];
+        if ((a > b) == up) {
+          s[lo] = b;
+          s[hi] = a;
+        }
+      }
+    }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const uint32_t *__restrict__ coords,
+                                              const float *__restrict__ vals) {
+  __shared__ uint64_t keys[kPrepCap];
+  __shared__ uint32_t bad;
+  __shared__ uint32_t nz;
+  const uint32_t q = blockIdx.x;
+  const uint64_t e0 = qd.qptr[q];
+  const uint64_t len64 = qd.qptr[q + 1] - e0;
+  if (threadIdx.x == 0) {
+    bad = len64 > (uint64_t)kPrepCap ? 1u : 0u;
+    nz = 0;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) {
+      qd.cnt[q] = 0;
+      qd.status[q] = 1;
+    }
+    return;
+  }
+  const int len = (int)len64;
+  int n = 1;
+  while (n < len) n <<= 1;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t key = ~0ull;
+    if (i < len) {
+      const uint32_t j = coords[e0 + i];
+      const float v = vals[e0 + i];
+      const uint32_t vb = __builtin_bit_cast(uint32_t, v);
+      const uint32_t ab = vb & 0x7FFFFFFFu;
+      if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
+      if (ab != 0u) {
+        atomicAdd(&nz, 1u);
+        key = ((uint64_t)(~ab) << 32) | ((uint64_t)(j & 0x7FFFFFFFu) << 1) | (uint64_t)(vb >> 31);
+      }
+    }
+    keys[i] = key;
+  }
+  __syncthreads();
+  // duplicate check: sort the coordinates alone, then compare neighbours
+  {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const uint64_t k = keys[i];
+      keys[i] = (k == ~0ull) ? ~0ull : ((k & 0xFFFFFFFFull) >> 1);  // j, zeros last
+    }
+    bitonic_sort_u64_asc(keys, n);
+    for (int i = threadIdx.x; i + 1 < n; i += blockDim.x)
+      if (keys[i] != ~0ull && keys[i] == keys[i + 1]) atomicOr(&bad, 1u);
+    __syncthreads();
+  }
+  if (bad) {
+    if (threadIdx.x == 0) {
+      qd.cnt[q] = 0;
+      qd.status[q] = 1;
+    }
+    return;
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    uint64_t key = ~0ull;
+    if (i < len) {
+      const uint32_t j = coords[e0 + i];
+      const uint32_t vb = __builtin_bit_cast(uint32_t, vals[e0 + i]);
+      const uint32_t ab = vb & 0x7FFFFFFFu;
+      if (ab != 0u) key = ((uint64_t)(~ab) << 32) | ((uint64_t)j << 1) | (uint64_t)(vb >> 31);
+    }
+    keys[i] = key;
+  }
+  bitonic_sort_u64_asc(keys, n);
+  const uint32_t cnt = nz;
+  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+    const uint64_t k = keys[i];
+    const uint32_t ab = ~(uint32_t)(k >> 32);
+    const uint32_t lo = (uint32_t)k;
+    const uint32_t j = lo >> 1;
+    const uint32_t vb = ab | ((lo & 1u) << 31);
+    qd.j[e0 + i] = j;
+    qd.q[e0 + i] = __builtin_bit_cast(float, vb);
+    for (uint32_t o = 0; o < ix.h; ++o) qd.b[(e0 + i) * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+  }
+  if (threadIdx.x == 0) {
+    qd.cnt[q] = cnt;
+    qd.status[q] = 0;
+  }
+}
+
+hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
+                       hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prep, dim3(nq), dim3(256), 0, s, ix, qd, coords, vals);
+  return hipGetLastError();
+}
+
+}  // namespace snn

@@ -1,0 +1,379 @@
+// Search kernels: Sinnamon scoring (Alg. 6, T = infinity) fused with a
+// per-tile top-k selection, and the merge of tile candidates into the final
+// top-k (Alg. 3 / Alg. 7 with k' = k).
+//
+// A workgroup owns one (query, doc tile) pair. The tile is 256 * R consecutive
+// slots: wave w, lane l, register r owns slot tile0 + 64 * (w * R + r) + l.
+// For each query coordinate j, in the order of Alg. 6, the wave reads the R
+// posting-bitmap words of its slots; each word is used directly as the
+// wavefront lane mask (inverse ballot), and every lane whose bit is set reads
+// its document's bound from sketch row pi(j) -- min over the U rows if q_j > 0,
+// max over the L rows otherwise -- and adds q_j * bound to its private
+// accumulator. A lane whose bit is clear loads from an out-of-range buffer
+// offset, which returns 0 without touching memory, so the add is an exact
+// no-op and the inner loop has no branches. Scores never leave registers.
+//
+// Selection keys are ord(score) << 32 | (0xFFFFFFFF - id), so a larger key
+// means a higher score, then a lower id. The tile first finds the k-th largest
+// 32-bit score key by a most-significant-bit-first binary radix select built on
+// wavefront ballots and popcounts (one workgroup reduction per bit, stopping as
+// soon as the selected set has exactly k members), resolves ties at the k-th
+// score by the lower id the same way, and writes at most k candidates. It then
+// raises the query's shared threshold to its k-th key: no document below it can
+// be in the global top-k, so later tiles keep fewer candidates.
+#include "snn_device.h"
+
+namespace snn {
+
+constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource, 32-bit data format
+constexpr int kOob = (int)0x80000000u;         // buffer offset past every range: load returns 0
+
+// Read-only arrays are read through the constant address space: with a
+// wave-uniform address the loads become scalar loads (s_load), so bitmap words
+// and query entries land in SGPRs and drive the lane masks directly.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T *p) {
+  return (cptr<T>)(p);
+}
+
+struct SelShared {
+  uint32_t red[2][kWaves];
+  uint32_t emit;
+  uint32_t item;
+};
+
+__device__ __forceinline__ uint32_t wg_sum(uint32_t v, SelShared &sh, int &par) {
+  if ((threadIdx.x & 63) == 0) sh.red[par][threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) s += sh.red[par][w];
+  par ^= 1;
+  return s;
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t w) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)w);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(w >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// k-th largest of the workgroup's keys (k >= 1, at least k keys non-zero).
+// Returns the threshold T. exact = true: {key >= T} has exactly k members.
+// exact = false: T is the k-th largest key itself, {key > T} has k - need
+// members and need >= 1 of the keys equal to T are still to be chosen.
+template <int R>
+__device__ uint32_t select_kth(const uint32_t (&key)[R], uint32_t k, SelShared &sh, int &par, bool &exact,
+                               uint32_t &need_out) {
+  uint32_t prefix = 0, need = k;
+  for (int bit = 31; bit >= 0; --bit) {
+    const uint32_t hm = 0xFFFFFFFFu << bit;
+    const uint32_t want = prefix | (1u << bit);
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((key[r] & hm) == want));
+    c = wg_sum(c, sh, par);
+    if (c >= need) {
+      prefix = want;
+      if (c == need) {
+        exact = true;
+        need_out = 0;
+        return prefix;
+      }
+    } else {
+      need -= c;
+    }
+  }
+  exact = false;
+  need_out = need;
+  return prefix;
+}
+
+template <int R>
+__device__ __forceinline__ uint32_t count_pred(const bool (&p)[R]) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(p[r]));
+  return c;
+}
+
+template <int R>
+__device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 64u * R;
+  const uint32_t wword0 = wslot0 >> 6;
+  const DevIndex &ix = a.ix;
+  const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
+  uint32_t *ccnt = a.cand_cnt + (size_t)q * a.tiles + t;
+  uint64_t *cout = a.cand + ((size_t)q * a.tiles + t) * a.kmax;
+
+  if (as_const(a.qd.status)[q] != 0u) {  // malformed query: no candidates
+    if (threadIdx.x == 0) *ccnt = 0;
+    return;
+  }
+
+  // ---------------- scoring (Alg. 6) ----------------
+  float acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+
+  const uint64_t e0 = as_const(a.qd.qptr)[q];
+  const uint32_t ne = as_const(a.qd.cnt)[q];
+  const uint32_t h = ix.h;
+  const cptr<uint32_t> qj = as_const(a.qd.j);
+  const cptr<float> qq = as_const(a.qd.q);
+  const cptr<uint32_t> qb = as_const(a.qd.b);
+  const cptr<uint64_t> bits = as_const(ix.bits);
+  const size_t cap = ix.cap;
+  for (uint32_t c = 0; c < ne; ++c) {
+    const uint32_t j = qj[e0 + c];
+    const float qv = qq[e0 + c];
+    const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
+    const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
+    if (h == 1) {
+      const __amdgpu_buffer_rsrc_t rs =
+          __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, R * 64 * 4, kBufFlags);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool on = __builtin_amdgcn_inverse_ballot_w64(wp[r]);
+        const int off = on ? (r * 64 + lane) * 4 : kOob;
+        const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        acc[r] = __builtin_fmaf(qv, v, acc[r]);
+      }
+    } else {
+      // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows
+      const bool upper = qv > 0.0f;
+      __amdgpu_buffer_rsrc_t rs0, rs1, rs2, rs3;
+      rs0 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h] * cap), 0, R * 256, kBufFlags);
+      rs1 = rs2 = rs3 = rs0;
+      if (h > 1) rs1 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 1] * cap), 0, R * 256, kBufFlags);
+      if (h > 2) rs2 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 2] * cap), 0, R * 256, kBufFlags);
+      if (h > 3) rs3 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 3] * cap), 0, R * 256, kBufFlags);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const bool on = __builtin_amdgcn_inverse_ballot_w64(wp[r]);
+        const int off = on ? (r * 64 + lane) * 4 : kOob;
+        // unused mappings repeat row 0, which leaves the min/max unchanged
+        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs0, off, 0, 0));
+        const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs1, off, 0, 0));
+        const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs2, off, 0, 0));
+        const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs3, off, 0, 0));
+        const float v = upper ? fminf(fminf(v0, v1), fminf(v2, v3)) : fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+        acc[r] = __builtin_fmaf(qv, v, acc[r]);
+      }
+    }
+  }
+
+  // ---------------- selection keys ----------------
+  uint32_t key[R];
+  const cptr<uint64_t> lw = as_const(ix.live) + wword0;
+  const uint32_t thr0 = __hip_atomic_load(&a.thr[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t thr = __builtin_amdgcn_readfirstlane(thr0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool lv = __builtin_amdgcn_inverse_ballot_w64(lw[r]);
+    const float s = acc[r] == 0.0f ? 0.0f : acc[r];  // -0 -> +0
+    const uint32_t kk = ord_key(s);
+    key[r] = (lv && kk >= thr) ? kk : 0u;
+  }
+  int par = 0;
+  uint32_t nvalid;
+  {
+    uint32_t c = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(key[r] != 0u));
+    nvalid = wg_sum(c, sh, par);
+  }
+
+  // Emission rule: mode 0 keeps every valid key; mode 1 keeps key >= T;
+  // mode 2 keeps key > T and, among key == T, the ids whose id key >= T2.
+  int mode = 0;
+  uint32_t T = 0, T2 = 0;
+  uint32_t idk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) idk[r] = 0u;
+  if (nvalid > kq) {
+    bool exact;
+    uint32_t need;
+    T = select_kth<R>(key, kq, sh, par, exact, need);
+    mode = 1;
+    if (!exact) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) c += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(key[r] == T));
+      const uint32_t nt = wg_sum(c, sh, par);
+      if (nt != need) {
+        // ties at the k-th score: keep the `need` lowest ids among them
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          idk[r] = key[r] == T ? (0xFFFFFFFFu - ix.slot2id[wslot0 + r * 64 + lane]) : 0u;
+        bool ex2;
+        uint32_t need2;
+        T2 = select_kth<R>(idk, need, sh, par, ex2, need2);
+        mode = 2;
+      }
+    }
+  }
+
+  // ---------------- emit candidates ----------------
+  if (threadIdx.x == 0) sh.emit = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool e = mode == 0 ? key[r] != 0u
+                             : (mode == 1 ? key[r] >= T : (key[r] > T || (key[r] == T && idk[r] >= T2)));
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(e);
+    if (mask == 0) continue;
+    uint32_t basepos = 0;
+    if (lane == 0) basepos = atomicAdd(&sh.emit, (uint32_t)__popcll(mask));
+    basepos = __builtin_amdgcn_readfirstlane(basepos);
+    if (e) {
+      const uint32_t pos = basepos + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+      const uint32_t id = ix.slot2id[wslot0 + r * 64 + lane];
+      cout[pos] = ((uint64_t)key[r] << 32) | (uint64_t)(0xFFFFFFFFu - id);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *ccnt = sh.emit;
+    if (mode != 0 && T > thr) atomicMax(&a.thr[q], T);
+  }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
+  __shared__ SelShared sh;
+  tile_body<R>(a, a.q0 + blockIdx.y, blockIdx.x, sh);
+}
+
+// Persistent form: a fixed grid pulls (query, tile) items from per-XCD queues.
+// Workgroups are dispatched round-robin over the XCDs, so workgroup b runs on
+// XCD b % xcds; queue x holds the tiles t with t % xcds == x, tile-major, so
+// the workgroups of one XCD work through one tile's bitmap and sketch slices
+// for many queries while those slices sit in that XCD's L2. A drained queue
+// steals from the others; every workgroup exits once all queues are drained.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
+  __shared__ SelShared sh;
+  const uint32_t X = a.xcds;
+  const uint32_t home = blockIdx.x % X;
+  const uint32_t nq = a.nq;
+  for (uint32_t step = 0; step < X; ++step) {
+    const uint32_t x = (home + step) % X;
+    const uint32_t tiles_x = a.tiles > x ? (a.tiles - x + X - 1) / X : 0u;
+    const uint32_t items = tiles_x * nq;
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) sh.item = atomicAdd(&a.queue[x], 1u);
+      __syncthreads();
+      const uint32_t it = sh.item;
+      if (it >= items) break;
+      const uint32_t t = x + X * (it / nq);
+      const uint32_t q = it % nq;
+      tile_body<R>(a, q, t, sh);
+    }
+  }
+}
+
+hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s) {
+  dim3 grid(a.tiles, nq_launch);
+  switch (R) {
+    case 16: hipLaunchKernelGGL(k_tiles<16>, grid, dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_tiles<32>, grid, dim3(kBlock), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_tiles<64>, grid, dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s) {
+  switch (R) {
+    case 16: hipLaunchKernelGGL(k_tiles_persistent<16>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_tiles_persistent<32>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_tiles_persistent<64>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Merge: one workgroup takes up to `fanin` candidate groups of one query,
+// sorts them by key descending in LDS (bitonic), and keeps the k best. The last
+// level writes (id, score) results; earlier levels write a smaller group list.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
+  __shared__ uint64_t s[kMergeCap];
+  __shared__ uint32_t off[257];
+  const uint32_t q = a.q0 + blockIdx.y;
+  const uint32_t g = blockIdx.x;
+  const uint32_t g0 = g * a.fanin;
+  const uint32_t g1 = min(g0 + a.fanin, a.groups_in);
+  const uint32_t ng = g1 > g0 ? g1 - g0 : 0u;
+  const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
+  // offsets of each input group inside the LDS list (fanin <= 256)
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t i = 0; i < ng; ++i) {
+      off[i] = acc;
+      acc += a.in_cnt[(size_t)q * a.groups_in + g0 + i];
+    }
+    off[ng] = acc;
+  }
+  __syncthreads();
+  const uint32_t M = off[ng];
+  int n = 1;
+  while (n < (int)M) n <<= 1;
+  for (uint32_t i = 0; i < ng; ++i) {
+    const uint32_t c = off[i + 1] - off[i];
+    const uint64_t *src = a.in + ((size_t)q * a.groups_in + g0 + i) * a.kmax;
+    for (uint32_t e = threadIdx.x; e < c; e += blockDim.x) s[off[i] + e] = src[e];
+  }
+  for (int e = (int)M + threadIdx.x; e < n; e += blockDim.x) s[e] = 0ull;
+  // bitonic sort, descending
+  for (int size = 2; size <= n; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool down = (lo & size) == 0;
+        const uint64_t x = s[lo], y = s[hi];
+        if ((x < y) == down) {
+          s[lo] = y;
+          s[hi] = x;
+        }
+      }
+    }
+  __syncthreads();
+  const bool bad = a.status && a.status[q] != 0u;
+  const uint32_t keep = bad ? 0u : min(M, kq);
+  if (a.groups_out > 1) {
+    uint64_t *dst = a.out + ((size_t)q * a.groups_out + g) * a.kmax;
+    for (uint32_t e = threadIdx.x; e < keep; e += blockDim.x) dst[e] = s[e];
+    if (threadIdx.x == 0) a.out_cnt[(size_t)q * a.groups_out + g] = keep;
+  } else {
+    uint32_t *ids = a.res_ids + (size_t)q * a.kmax;
+    float *sc = a.res_scores + (size_t)q * a.kmax;
+    for (uint32_t e = threadIdx.x; e < keep; e += blockDim.x) {
+      const uint64_t key = s[e];
+      ids[e] = 0xFFFFFFFFu - (uint32_t)key;
+      sc[e] = key_value((uint32_t)(key >> 32));
+    }
+    if (threadIdx.x == 0) {
+      a.res_cnt[q] = keep;
+      if (a.fallback) a.fallback[q] = (!bad && a.keff && M < a.keff[q]) ? 1u : 0u;
+    }
+  }
+}
+
+hipError_t launch_merge(const MergeArgs &a, hipStream_t s) {
+  if (a.fanin > 256 || (uint64_t)a.fanin * a.kmax > (uint64_t)kMergeCap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_merge, dim3(a.groups_out, a.nq), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace snn

@@ -1,0 +1,631 @@
+// Host side of the C ABI (include/snn.h): the slot store, input validation,
+// staging of host inputs, and the orchestration of the search kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "snn.h"
+#include "snn_device.h"
+#include "snn_host.h"
+
+using namespace snn;
+
+static constexpr uint32_t kMaxGridY = 65535;
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+namespace snn {
+
+uint64_t splitmix64_mix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+hipError_t DevBuf::ensure(size_t bytes, hipStream_t s) {
+  if (bytes <= cap) return hipSuccess;
+  if (p) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  size_t want = bytes + bytes / 4 + 4096;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+hipError_t PinBuf::ensure(size_t bytes, hipStream_t s) {
+  if (bytes <= cap) return hipSuccess;
+  if (p) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  size_t want = bytes + bytes / 4 + 4096;
+  hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    p = nullptr;
+    return e;
+  }
+  cap = want;
+  return hipSuccess;
+}
+
+void PinBuf::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  cap = 0;
+}
+
+}  // namespace snn
+
+snn_status snn_index::fail(snn_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  err = buf;
+  return st;
+}
+
+snn_status snn_index::hip_fail(hipError_t e, const char *what) {
+  if (e == hipErrorOutOfMemory) return fail(SNN_E_NOMEM, "%s: out of device memory", what);
+  return fail(SNN_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(ix, call, what)                 \
+  do {                                          \
+    hipError_t e__ = (call);                    \
+    if (e__ != hipSuccess) return (ix)->hip_fail(e__, what); \
+  } while (0)
+
+// Validate one sparse vector; appends its non-zero entries to out_c/out_v.
+static bool check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v, std::vector<uint32_t> &oc,
+                         std::vector<float> &ov, std::vector<uint32_t> &scratch, const char *what) {
+  if (nnz && (!c || !v)) {
+    ix->fail(SNN_E_INVALID, "%s: null coordinate or value pointer", what);
+    return false;
+  }
+  scratch.clear();
+  for (uint32_t t = 0; t < nnz; ++t) {
+    if (c[t] >= ix->cfg.dim) {
+      ix->fail(SNN_E_INVALID, "%s: coordinate %u >= dim %u", what, c[t], ix->cfg.dim);
+      return false;
+    }
+    if (!std::isfinite(v[t])) {
+      ix->fail(SNN_E_INVALID, "%s: non-finite value at coordinate %u", what, c[t]);
+      return false;
+    }
+    scratch.push_back(c[t]);
+  }
+  std::sort(scratch.begin(), scratch.end());
+  for (size_t t = 1; t < scratch.size(); ++t)
+    if (scratch[t] == scratch[t - 1]) {
+      ix->fail(SNN_E_INVALID, "%s: duplicate coordinate %u", what, scratch[t]);
+      return false;
+    }
+  for (uint32_t t = 0; t < nnz; ++t)
+    if (v[t] != 0.0f) {
+      oc.push_back(c[t]);
+      ov.push_back(v[t]);
+    }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy
+// ---------------------------------------------------------------------------
+extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_index **out) {
+  if (!out) return SNN_E_INVALID;
+  *out = nullptr;
+  if (!cfg || cfg->dim == 0 || cfg->m == 0 || cfg->h == 0 || cfg->h > 4 || cfg->capacity == 0 ||
+      cfg->capacity > (1u << 31) || cfg->flags != 0 || cfg->dim >= (1u << 31))
+    return SNN_E_INVALID;
+  snn_index *ix = new (std::nothrow) snn_index();
+  if (!ix) return SNN_E_NOMEM;
+  ix->cfg = *cfg;
+  ix->cap = (uint32_t)(((uint64_t)cfg->capacity + kTileMax - 1) / kTileMax * kTileMax);
+  ix->W = ix->cap / 64;
+  ix->stream = (hipStream_t)hip_stream;
+  DevIndex &d = ix->dev;
+  d.dim = cfg->dim;
+  d.m = cfg->m;
+  d.h = cfg->h;
+  d.cap = ix->cap;
+  d.W = ix->W;
+  size_t bits_bytes = (size_t)cfg->dim * ix->W * 8;
+  size_t sk_bytes = (size_t)cfg->m * ix->cap * 4;
+  hipError_t e = hipSuccess;
+  if ((e = hipMalloc(&d.bits, bits_bytes)) != hipSuccess || (e = hipMalloc(&d.live, (size_t)ix->W * 8)) != hipSuccess ||
+      (e = hipMalloc(&d.U, sk_bytes)) != hipSuccess || (e = hipMalloc(&d.L, sk_bytes)) != hipSuccess ||
+      (e = hipMalloc(&d.slot2id, (size_t)ix->cap * 4)) != hipSuccess ||
+      (e = hipMalloc(&d.bucket, (size_t)cfg->h * cfg->dim * 4)) != hipSuccess) {
+    snn_status st = e == hipErrorOutOfMemory ? SNN_E_NOMEM : SNN_E_DEVICE;
+    snn_destroy(ix);
+    return st;
+  }
+  // zero bitmaps and sketches; slot2id = reserved id
+  if (hipMemsetAsync(d.bits, 0, bits_bytes, ix->stream) != hipSuccess ||
+      hipMemsetAsync(d.live, 0, (size_t)ix->W * 8, ix->stream) != hipSuccess ||
+      hipMemsetAsync(d.U, 0, sk_bytes, ix->stream) != hipSuccess ||
+      hipMemsetAsync(d.L, 0, sk_bytes, ix->stream) != hipSuccess ||
+      launch_fill_u32(d.slot2id, 0xFFFFFFFFu, ix->cap, ix->stream) != hipSuccess) {
+    snn_destroy(ix);
+    return SNN_E_DEVICE;
+  }
+  // the random mappings pi_o(j) = mix64(mix64(seed + o) ^ j) mod m
+  std::vector<uint32_t> tab((size_t)cfg->h * cfg->dim);
+  for (uint32_t o = 0; o < cfg->h; ++o) {
+    const uint64_t so = splitmix64_mix(cfg->hash_seed + o);
+    for (uint32_t j = 0; j < cfg->dim; ++j)
+      tab[(size_t)o * cfg->dim + j] = (uint32_t)(splitmix64_mix(so ^ (uint64_t)j) % cfg->m);
+  }
+  if (hipMemcpyAsync(d.bucket, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, ix->stream) != hipSuccess ||
+      hipStreamSynchronize(ix->stream) != hipSuccess) {
+    snn_destroy(ix);
+    return SNN_E_DEVICE;
+  }
+  ix->slot_id.assign(ix->cap, 0xFFFFFFFFu);
+  ix->fwd.resize(ix->cap);
+  ix->tune_init();
+  *out = ix;
+  return SNN_OK;
+}
+
+extern "C" void snn_destroy(snn_index *ix) {
+  if (!ix) return;
+  if (ix->stream) (void)hipStreamSynchronize(ix->stream);
+  else (void)hipDeviceSynchronize();
+  ix->release_extras();
+  DevIndex &d = ix->dev;
+  if (d.bits) (void)hipFree(d.bits);
+  if (d.live) (void)hipFree(d.live);
+  if (d.U) (void)hipFree(d.U);
+  if (d.L) (void)hipFree(d.L);
+  if (d.slot2id) (void)hipFree(d.slot2id);
+  if (d.bucket) (void)hipFree(d.bucket);
+  ix->up.release();
+  ix->pin.release();
+  ix->ws.release();
+  ix->cand.release();
+  ix->cand2.release();
+  delete ix;
+}
+
+extern "C" size_t snn_live_count(const snn_index *ix) { return ix ? ix->live : 0; }
+
+extern "C" const char *snn_last_error(const snn_index *ix) {
+  if (!ix) return "null index";
+  return ix->err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// insert / delete
+// ---------------------------------------------------------------------------
+snn_status snn_index::upload_and_insert(const std::vector<uint32_t> &slots, const std::vector<uint32_t> &ids,
+                                        const std::vector<uint64_t> &indptr, const std::vector<uint32_t> &coords,
+                                        const std::vector<float> &vals, size_t r0, size_t r1) {
+  const size_t n = r1 - r0;
+  const uint64_t e0 = indptr[r0], e1 = indptr[r1];
+  const size_t ne = (size_t)(e1 - e0);
+  const size_t bytes = n * 4 * 2 + (n + 1) * 8 + ne * 8 + 64;
+  HIP_TRY(this, pin.ensure(bytes, stream), "insert staging");
+  HIP_TRY(this, up.ensure(bytes, stream), "insert upload");
+  char *hp = (char *)pin.p;
+  size_t o_slots = 0, o_ids = n * 4, o_ptr = (o_ids + n * 4 + 7) / 8 * 8, o_c = o_ptr + (n + 1) * 8, o_v = o_c + ne * 4;
+  memcpy(hp + o_slots, slots.data() + r0, n * 4);
+  memcpy(hp + o_ids, ids.data() + r0, n * 4);
+  uint64_t *ip = (uint64_t *)(hp + o_ptr);
+  for (size_t r = 0; r <= n; ++r) ip[r] = indptr[r0 + r] - e0;
+  memcpy(hp + o_c, coords.data() + e0, ne * 4);
+  memcpy(hp + o_v, vals.data() + e0, ne * 4);
+  char *dp = (char *)up.p;
+  HIP_TRY(this, hipMemcpyAsync(dp, hp, o_v + ne * 4, hipMemcpyHostToDevice, stream), "insert copy");
+  HIP_TRY(this,
+          launch_insert(dev, (uint32_t)n, (uint32_t *)(dp + o_slots), (uint32_t *)(dp + o_ids),
+                        (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v), stream),
+          "insert kernel");
+  HIP_TRY(this, hipStreamSynchronize(stream), "insert sync");
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t *ids, const uint64_t *indptr,
+                                       const uint32_t *coords, const float *vals) {
+  if (!ix) return SNN_E_INVALID;
+  if (n == 0) return SNN_OK;
+  if (!ids || !indptr) return ix->fail(SNN_E_INVALID, "insert: null ids or indptr");
+  // validate everything first (all-or-nothing)
+  std::vector<uint32_t> oc, scratch, slot_of(n);
+  std::vector<float> ov;
+  std::vector<uint64_t> optr(n + 1, 0);
+  std::unordered_map<uint32_t, uint32_t> seen;
+  for (uint32_t r = 0; r < n; ++r) {
+    if (ids[r] == 0xFFFFFFFFu) return ix->fail(SNN_E_INVALID, "insert: id 0xFFFFFFFF is reserved");
+    if (ix->id2slot.count(ids[r])) return ix->fail(SNN_E_EXISTS, "insert: id %u is already live", ids[r]);
+    if (!seen.emplace(ids[r], r).second) return ix->fail(SNN_E_INVALID, "insert: id %u twice in one batch", ids[r]);
+    if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "insert: indptr not monotone");
+    uint64_t len = indptr[r + 1] - indptr[r];
+    if (len > ix->cfg.dim) return ix->fail(SNN_E_INVALID, "insert: vector with more entries than dim");
+    if (!check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "insert"))
+      return SNN_E_INVALID;
+    optr[r + 1] = oc.size();
+  }
+  size_t avail = ix->free_slots.size() + (ix->cap - ix->next_fresh);
+  if (n > avail) return ix->fail(SNN_E_FULL, "insert: %u vectors but only %zu free slots", n, avail);
+  // assign slots: reuse freed columns first (Section 4.3), then fresh ones
+  std::vector<uint32_t> vid(ids, ids + n);
+  for (uint32_t r = 0; r < n; ++r) {
+    if (!ix->free_slots.empty()) {
+      slot_of[r] = ix->free_slots.back();
+      ix->free_slots.pop_back();
+    } else {
+      slot_of[r] = ix->next_fresh++;
+    }
+  }
+  // upload in chunks of at most ~16M entries
+  const size_t kChunk = (size_t)16 << 20;
+  size_t r0 = 0;
+  while (r0 < n) {
+    size_t r1 = r0 + 1;
+    while (r1 < n && optr[r1 + 1] - optr[r0] <= kChunk && r1 - r0 < (1u << 20)) ++r1;
+    snn_status st = ix->upload_and_insert(slot_of, vid, optr, oc, ov, r0, r1);
+    if (st != SNN_OK) return st;  // device error: the index is no longer consistent
+    r0 = r1;
+  }
+  for (uint32_t r = 0; r < n; ++r) {
+    const uint32_t s = slot_of[r];
+    ix->id2slot[ids[r]] = s;
+    ix->slot_id[s] = ids[r];
+    ix->fwd[s].assign(oc.begin() + optr[r], oc.begin() + optr[r + 1]);
+  }
+  ix->live += n;
+  ix->mutations++;
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_insert(snn_index *ix, uint32_t id, uint32_t nnz, const uint32_t *coords, const float *vals) {
+  uint64_t ip[2] = {0, nnz};
+  return snn_insert_batch(ix, 1, &id, ip, coords, vals);
+}
+
+extern "C" snn_status snn_delete_batch(snn_index *ix, uint32_t n, const uint32_t *ids) {
+  if (!ix) return SNN_E_INVALID;
+  if (n == 0) return SNN_OK;
+  if (!ids) return ix->fail(SNN_E_INVALID, "delete: null ids");
+  std::vector<uint32_t> slots(n);
+  std::unordered_map<uint32_t, int> seen;
+  for (uint32_t r = 0; r < n; ++r) {
+    auto it = ix->id2slot.find(ids[r]);
+    if (it == ix->id2slot.end()) return ix->fail(SNN_E_NOT_FOUND, "delete: id %u is not live", ids[r]);
+    if (!seen.emplace(ids[r], 1).second) return ix->fail(SNN_E_INVALID, "delete: id %u twice in one batch", ids[r]);
+    slots[r] = it->second;
+  }
+  std::vector<uint64_t> ptr(n + 1, 0);
+  std::vector<uint32_t> co;
+  for (uint32_t r = 0; r < n; ++r) {
+    const auto &f = ix->fwd[slots[r]];
+    co.insert(co.end(), f.begin(), f.end());
+    ptr[r + 1] = co.size();
+  }
+  snn_status st = ix->upload_and_delete(slots, ptr, co, 1, 1);
+  if (st != SNN_OK) return st;
+  for (uint32_t r = 0; r < n; ++r) {
+    const uint32_t s = slots[r];
+    ix->id2slot.erase(ids[r]);
+    ix->slot_id[s] = 0xFFFFFFFFu;
+    ix->fwd[s].clear();
+    ix->fwd[s].shrink_to_fit();
+    ix->free_slots.push_back(s);
+  }
+  ix->live -= n;
+  ix->mutations++;
+  return SNN_OK;
+}
+
+snn_status snn_index::upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
+                                        const std::vector<uint32_t> &co, int clear_bits, int clear_live) {
+  const size_t n = slots.size(), ne = co.size();
+  const size_t bytes = n * 4 + 8 + (n + 1) * 8 + ne * 4 + 64;
+  HIP_TRY(this, pin.ensure(bytes, stream), "delete staging");
+  HIP_TRY(this, up.ensure(bytes, stream), "delete upload");
+  char *hp = (char *)pin.p;
+  size_t o_ptr = (n * 4 + 7) / 8 * 8, o_c = o_ptr + (n + 1) * 8;
+  memcpy(hp, slots.data(), n * 4);
+  memcpy(hp + o_ptr, ptr.data(), (n + 1) * 8);
+  if (ne) memcpy(hp + o_c, co.data(), ne * 4);
+  char *dp = (char *)up.p;
+  HIP_TRY(this, hipMemcpyAsync(dp, hp, o_c + ne * 4, hipMemcpyHostToDevice, stream), "delete copy");
+  HIP_TRY(this,
+          launch_delete(dev, (uint32_t)n, (uint32_t *)dp, (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), clear_bits,
+                        clear_live, stream),
+          "delete kernel");
+  HIP_TRY(this, hipStreamSynchronize(stream), "delete sync");
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete_batch(ix, 1, &id); }
+
+// ---------------------------------------------------------------------------
+// search
+// ---------------------------------------------------------------------------
+
+// Device workspace for one batch: prepared entries, per-query state, tile
+// candidates. Laid out in one allocation.
+snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, SearchWs &w) {
+  const uint32_t h = cfg.h;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  size_t o = 0;
+  const size_t o_cnt = o; o += al((size_t)nq * 4);
+  const size_t o_status = o; o += al((size_t)nq * 4);
+  const size_t o_thr = o; o += al((size_t)nq * 4);
+  const size_t o_fb = o; o += al((size_t)nq * 4);
+  const size_t o_keff = o; o += al((size_t)nq * 4);
+  const size_t o_j = o; o += al((size_t)total * 4);
+  const size_t o_q = o; o += al((size_t)total * 4);
+  const size_t o_b = o; o += al((size_t)total * 4 * h);
+  const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
+  const size_t o_cc2 = o; o += al((size_t)nq * tiles * 4);
+  const size_t o_queue = o; o += al(64 * 4);
+  HIP_TRY(this, ws.ensure(o, stream), "search workspace");
+  const uint32_t F = merge_fanin(k);
+  const uint32_t g1 = (tiles + F - 1) / F;
+  HIP_TRY(this, cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
+  HIP_TRY(this, cand2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 8 + 64, stream), "candidate buffer");
+  char *p = (char *)ws.p;
+  w.cnt = (uint32_t *)(p + o_cnt);
+  w.status = (uint32_t *)(p + o_status);
+  w.thr = (uint32_t *)(p + o_thr);
+  w.fallback = (uint32_t *)(p + o_fb);
+  w.keff = (uint32_t *)(p + o_keff);
+  w.j = (uint32_t *)(p + o_j);
+  w.q = (float *)(p + o_q);
+  w.b = (uint32_t *)(p + o_b);
+  w.cand_cnt = (uint32_t *)(p + o_cc);
+  w.cand_cnt2 = (uint32_t *)(p + o_cc2);
+  w.queue = (uint32_t *)(p + o_queue);
+  w.cand = (uint64_t *)cand.p;
+  w.cand2 = (uint64_t *)cand2.p;
+  return SNN_OK;
+}
+
+uint32_t snn_index::merge_fanin(uint32_t k) const {
+  uint32_t F = (uint32_t)kMergeCap / std::max<uint32_t>(k, 1);
+  if (F > 256) F = 256;
+  if (F < 2) F = 2;
+  return F;
+}
+
+// Enqueue the merge levels for queries [q0, q0 + nqm).
+snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
+                                    uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids,
+                                    float *res_scores, uint32_t *res_cnt, hipStream_t s) {
+  const uint32_t F = merge_fanin(k);
+  uint32_t G = tiles;
+  const uint64_t *in = w.cand;
+  const uint32_t *in_cnt = w.cand_cnt;
+  uint64_t *bufs[2] = {w.cand2, w.cand};
+  uint32_t *cnts[2] = {w.cand_cnt2, w.cand_cnt};
+  int lvl = 0;
+  for (;;) {
+    MergeArgs m{};
+    m.nq = nqm;
+    m.q0 = q0;
+    m.groups_in = G;
+    m.fanin = std::min(F, G);
+    m.groups_out = (G + m.fanin - 1) / m.fanin;
+    m.kmax = k;
+    m.kq = kq;
+    m.keff = keff;
+    m.in = in;
+    m.in_cnt = in_cnt;
+    m.status = w.status;
+    if (m.groups_out > 1) {
+      m.out = bufs[lvl & 1];
+      m.out_cnt = cnts[lvl & 1];
+    } else {
+      m.res_ids = res_ids;
+      m.res_scores = res_scores;
+      m.res_cnt = res_cnt;
+      m.fallback = w.fallback;
+    }
+    (void)nq_total;
+    for (uint32_t c0 = 0; c0 < nqm; c0 += kMaxGridY) {
+      m.q0 = q0 + c0;
+      m.nq = std::min<uint32_t>(kMaxGridY, nqm - c0);
+      HIP_TRY(this, launch_merge(m, s), "merge kernel");
+    }
+    if (m.groups_out == 1) break;
+    in = m.out;
+    in_cnt = m.out_cnt;
+    G = m.groups_out;
+    ++lvl;
+  }
+  return SNN_OK;
+}
+
+snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
+                                 const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
+                                 uint32_t *d_cnt, hipStream_t s, const uint32_t *d_thr_init) {
+  const int R = mode == SNN_MODE_PLAIN ? tune.R_plain : tune.R_batch;
+  const uint32_t tile_docs = (uint32_t)kBlock * R;
+  const uint32_t tiles = (next_fresh + tile_docs - 1) / tile_docs;
+  if (tiles == 0) {
+    HIP_TRY(this, launch_fill_u32(d_cnt, 0u, nq, s), "fill");
+    return SNN_OK;
+  }
+  SearchWs w;
+  snn_status st = prepare_workspace(nq, total, k, tiles, w);
+  if (st != SNN_OK) return st;
+  last_ws = w;
+  QueryDesc qd{d_ptr, w.cnt, w.status, w.j, w.q, w.b};
+  HIP_TRY(this, launch_prep(dev, qd, nq, d_c, d_v, s), "prep kernel");
+  if (d_thr_init) {
+    HIP_TRY(this, hipMemcpyAsync(w.thr, d_thr_init, (size_t)nq * 4, hipMemcpyDeviceToDevice, s), "thr init");
+  } else {
+    HIP_TRY(this, launch_fill_u32(w.thr, 0u, nq, s), "thr fill");
+  }
+  TileArgs a{};
+  a.ix = dev;
+  a.qd = qd;
+  a.nq = nq;
+  a.tiles = tiles;
+  a.kmax = k;
+  a.kq = nullptr;
+  a.thr = w.thr;
+  a.cand = w.cand;
+  a.cand_cnt = w.cand_cnt;
+  a.queue = w.queue;
+  a.xcds = 8;
+  if (mode == SNN_MODE_PLAIN) {
+    for (uint32_t q = 0; q < nq; ++q) {
+      a.q0 = q;
+      HIP_TRY(this, launch_tiles(a, R, 1, s), "tile kernel");
+      st = enqueue_merge(w, nq, q, 1, tiles, k, nullptr, nullptr, d_ids, d_sc, d_cnt, s);
+      if (st != SNN_OK) return st;
+    }
+  } else {
+    a.q0 = 0;
+    if (tune.persistent) {
+      HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
+      HIP_TRY(this, launch_tiles_persistent(a, R, tune.grid, s), "persistent tile kernel");
+    } else {
+      for (uint32_t c0 = 0; c0 < nq; c0 += kMaxGridY) {
+        a.q0 = c0;
+        HIP_TRY(this, launch_tiles(a, R, std::min<uint32_t>(kMaxGridY, nq - c0), s), "tile kernel");
+      }
+    }
+    st = enqueue_merge(w, nq, 0, nq, tiles, k, nullptr, d_thr_init ? w.keff : nullptr, d_ids, d_sc, d_cnt, s);
+    if (st != SNN_OK) return st;
+  }
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                       const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
+                                       uint32_t *out_counts) {
+  if (!ix) return SNN_E_INVALID;
+  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
+  if (nq == 0) return SNN_OK;
+  if (!indptr || !out_ids || !out_scores || !out_counts) return ix->fail(SNN_E_INVALID, "search: null pointer");
+  std::vector<uint32_t> oc, scratch;
+  std::vector<float> ov;
+  for (uint32_t r = 0; r < nq; ++r) {
+    if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "search: indptr not monotone");
+    uint64_t len = indptr[r + 1] - indptr[r];
+    if (len > (uint64_t)kPrepCap) return ix->fail(SNN_E_INVALID, "search: a query has more than %d entries", kPrepCap);
+    oc.clear();
+    ov.clear();
+    if (!check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "search"))
+      return SNN_E_INVALID;
+  }
+  const uint64_t total = indptr[nq];
+  hipStream_t s = ix->stream;
+  const size_t in_bytes = ((size_t)(nq + 1) * 8 + total * 8 + 255) / 256 * 256 + 256;
+  const size_t out_bytes = (size_t)nq * k * 8 + (size_t)nq * 4 + 64;
+  HIP_TRY(ix, ix->pin.ensure(in_bytes + out_bytes, s), "search staging");
+  HIP_TRY(ix, ix->up.ensure(in_bytes + out_bytes, s), "search upload");
+  char *hp = (char *)ix->pin.p, *dp = (char *)ix->up.p;
+  const size_t o_c = (size_t)(nq + 1) * 8, o_v = o_c + total * 4, o_out = (o_v + total * 4 + 255) / 256 * 256;
+  memcpy(hp, indptr, (size_t)(nq + 1) * 8);
+  // the kernels index entries from 0: rebase the offsets
+  uint64_t base = indptr[0];
+  for (uint32_t r = 0; r <= nq; ++r) ((uint64_t *)hp)[r] -= base;
+  if (total - base) {
+    memcpy(hp + o_c, coords + base, (total - base) * 4);
+    memcpy(hp + o_v, vals + base, (total - base) * 4);
+  }
+  HIP_TRY(ix, hipMemcpyAsync(dp, hp, o_v + (total - base) * 4, hipMemcpyHostToDevice, s), "search copy");
+  uint32_t *d_ids = (uint32_t *)(dp + o_out);
+  float *d_sc = (float *)(d_ids + (size_t)nq * k);
+  uint32_t *d_cnt = (uint32_t *)(d_sc + (size_t)nq * k);
+  snn_status st = ix->run_search(nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v), k,
+                                 SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, nullptr);
+  if (st != SNN_OK) return st;
+  HIP_TRY(ix, hipMemcpyAsync(hp + o_out, d_ids, out_bytes - 64, hipMemcpyDeviceToHost, s), "search readback");
+  HIP_TRY(ix, hipStreamSynchronize(s), "search sync");
+  const uint32_t *h_ids = (const uint32_t *)(hp + o_out);
+  const float *h_sc = (const float *)(h_ids + (size_t)nq * k);
+  const uint32_t *h_cnt = (const uint32_t *)(h_sc + (size_t)nq * k);
+  memcpy(out_ids, h_ids, (size_t)nq * k * 4);
+  memcpy(out_scores, h_sc, (size_t)nq * k * 4);
+  memcpy(out_counts, h_cnt, (size_t)nq * 4);
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_search(snn_index *ix, uint32_t nnz, const uint32_t *coords, const float *vals, uint32_t k,
+                                 uint32_t *out_ids, float *out_scores, uint32_t *out_count) {
+  uint64_t ip[2] = {0, nnz};
+  return snn_search_batch(ix, 1, ip, coords, vals, k, out_ids, out_scores, out_count);
+}
+
+extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                           const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
+                                           float *out_scores, uint32_t *out_counts, void *stream) {
+  if (!ix) return SNN_E_INVALID;
+  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
+  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
+  if (mode > SNN_MODE_LEARNED) return ix->fail(SNN_E_INVALID, "search: unknown mode %u", mode);
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  uint64_t last = 0;
+  HIP_TRY(ix, hipMemcpyAsync(&last, indptr + nq, 8, hipMemcpyDeviceToHost, s), "indptr readback");
+  HIP_TRY(ix, hipStreamSynchronize(s), "indptr sync");
+  ix->last_nq = nq;
+  ix->last_mode = mode;
+  if (mode == SNN_MODE_LEARNED) return ix->search_learned(nq, indptr, last, coords, vals, k, out_ids, out_scores, out_counts, s);
+  return ix->run_search(nq, indptr, last, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, nullptr);
+}
+
+extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {
+  if (!ix) return SNN_E_INVALID;
+  uint32_t inv = 0;
+  if (ix->last_nq && ix->last_ws.status) {
+    std::vector<uint32_t> st(ix->last_nq);
+    HIP_TRY(ix, hipMemcpy(st.data(), ix->last_ws.status, (size_t)ix->last_nq * 4, hipMemcpyDeviceToHost), "status readback");
+    for (uint32_t v : st) inv += v != 0;
+  }
+  if (invalid_queries) *invalid_queries = inv;
+  if (fallbacks) *fallbacks = ix->last_fallbacks;
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_bucket_table(snn_index *ix, uint32_t *out) {
+  if (!ix || !out) return SNN_E_INVALID;
+  HIP_TRY(ix, hipMemcpy(out, ix->dev.bucket, (size_t)ix->cfg.h * ix->cfg.dim * 4, hipMemcpyDeviceToHost), "bucket readback");
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l) {
+  if (!ix || !u || !l) return SNN_E_INVALID;
+  auto it = ix->id2slot.find(id);
+  if (it == ix->id2slot.end()) return ix->fail(SNN_E_NOT_FOUND, "read_sketch: id %u is not live", id);
+  const uint32_t s = it->second;
+  HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
+  HIP_TRY(ix, hipMemcpy2D(u, 4, ix->dev.U + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "U readback");
+  HIP_TRY(ix, hipMemcpy2D(l, 4, ix->dev.L + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "L readback");
+  return SNN_OK;
+}

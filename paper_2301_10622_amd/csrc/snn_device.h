@@ -1,0 +1,110 @@
+// Device-side data layout and kernel entry points of the Sinnamon library.
+//
+// Layout in HBM (one index):
+//   bits     uint64 [dim][W]      posting bitmaps: bit s of row j is set when the
+//                                 document in slot s has coordinate j in nz(x)
+//                                 (the id-only inverted index I[j] of Section 4.1,
+//                                 stored as a bitmap over slots; W = cap / 64)
+//   live     uint64 [W]           bit s set when slot s holds a live document
+//   U, L     float  [m][cap]      the sketch matrix halves, one contiguous row per
+//                                 bucket (the transposed layout of Section 4.1)
+//   slot2id  uint32 [cap]         external id of the document in each slot
+//   bucket   uint32 [h][dim]      the random mappings pi_o(j)
+//
+// One 64-bit bitmap word covers 64 consecutive slots, which is exactly one
+// wavefront of 64 lanes: lane l owns slot 64*w + l, so the word is the wave's
+// execution mask for that coordinate and no lane ever contends with another
+// for a score.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snn {
+
+constexpr int kWaves = 4;               // waves per workgroup
+constexpr int kBlock = 64 * kWaves;      // threads per workgroup
+constexpr uint32_t kTileMax = 16384;     // largest tile (docs); capacity is a multiple
+constexpr int kMergeCap = 8192;          // candidates one merge workgroup sorts in LDS
+constexpr int kPrepCap = 4096;           // max non-zeros of one query
+constexpr uint32_t kMaxK = 4096;
+
+struct DevIndex {
+  uint64_t *bits;
+  uint64_t *live;
+  float *U;
+  float *L;
+  uint32_t *slot2id;
+  uint32_t *bucket;
+  uint32_t dim, m, h, cap, W;
+};
+
+// Prepared queries (Alg. 6 first steps): entry e of query q sits at qptr[q] + i
+// for i < cnt[q], sorted by |q_j| descending, ties by lower j.
+struct QueryDesc {
+  const uint64_t *qptr;  // [nq + 1] (the caller's CSR offsets)
+  uint32_t *cnt;         // [nq] non-zero entries after preparation
+  uint32_t *status;      // [nq] 0 = ok, else malformed
+  uint32_t *j;           // [total]
+  float *q;              // [total]
+  uint32_t *b;           // [total * h]
+};
+
+struct TileArgs {
+  DevIndex ix;
+  QueryDesc qd;
+  uint32_t nq;        // queries in the batch
+  uint32_t q0;        // first query of this launch
+  uint32_t tiles;     // active tiles (covering slots below the high-water mark)
+  uint32_t kmax;      // candidate stride per (query, tile)
+  const uint32_t *kq; // per-query k (nullable: kmax for all)
+  uint32_t *thr;      // [nq] shared inclusive lower bound on the k-th key (0 = none)
+  uint64_t *cand;     // [nq][tiles][kmax]
+  uint32_t *cand_cnt; // [nq][tiles]
+  // persistent schedule
+  uint32_t *queue;    // [8] per-XCD work counters (zeroed before launch)
+  uint32_t xcds;      // number of per-XCD queues
+};
+
+struct MergeArgs {
+  uint32_t nq;
+  uint32_t q0;
+  uint32_t groups_in;   // groups per query in the input
+  uint32_t fanin;       // input groups merged by one workgroup
+  uint32_t groups_out;  // groups per query in the output (1 = final)
+  uint32_t kmax;        // stride of a group
+  const uint32_t *kq;   // per-query k (nullable)
+  const uint32_t *keff; // per-query required count for the filter check (nullable)
+  const uint64_t *in;
+  const uint32_t *in_cnt;
+  uint64_t *out;        // next level (when groups_out > 1)
+  uint32_t *out_cnt;
+  uint32_t *res_ids;    // final level: [nq][kmax]
+  float *res_scores;
+  uint32_t *res_cnt;    // [nq]
+  uint32_t *fallback;   // [nq] set to 1 when fewer than keff candidates survived
+  const uint32_t *status; // [nq] malformed queries produce 0 results
+};
+
+// order-preserving float -> uint32 map (negative floats reversed); 0 never occurs for finite x
+__host__ __device__ inline uint32_t ord_key(float x) {
+  uint32_t b = __builtin_bit_cast(uint32_t, x);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ inline float key_value(uint32_t k) {
+  uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __builtin_bit_cast(float, b);
+}
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
+                         const uint64_t *indptr, const uint32_t *coords, const float *vals, hipStream_t s);
+hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,
+                         const uint32_t *coords, int clear_bits, int clear_live, hipStream_t s);
+hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
+                       hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
+hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
+hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
+hipError_t launch_merge(const MergeArgs &a, hipStream_t s);
+
+}  // namespace snn

@@ -1,0 +1,97 @@
+// Host-side state of one index (the opaque snn_index of include/snn.h).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "snn.h"
+#include "snn_device.h"
+
+namespace snn {
+
+uint64_t splitmix64_mix(uint64_t z);
+
+// grow-only device buffer; growing synchronises the stream before freeing
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes, hipStream_t s);
+  void release();
+};
+
+struct PinBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes, hipStream_t s);
+  void release();
+};
+
+struct SearchWs {
+  uint32_t *cnt = nullptr, *status = nullptr, *thr = nullptr, *fallback = nullptr, *keff = nullptr;
+  uint32_t *j = nullptr, *b = nullptr;
+  float *q = nullptr;
+  uint32_t *cand_cnt = nullptr, *cand_cnt2 = nullptr, *queue = nullptr;
+  uint64_t *cand = nullptr, *cand2 = nullptr;
+};
+
+// Launch schedule of the search kernels (set by the autotuner).
+struct Tune {
+  int R_plain = 16;      // registers (64-doc groups) per lane, plain mode
+  int R_batch = 32;      // same, batched mode
+  bool persistent = true;
+  uint32_t grid = 2048;  // persistent grid
+};
+
+struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
+
+}  // namespace snn
+
+struct snn_index {
+  snn_config cfg{};
+  uint32_t cap = 0, W = 0;
+  hipStream_t stream = nullptr;
+  snn::DevIndex dev{};
+
+  // slot store
+  std::unordered_map<uint32_t, uint32_t> id2slot;
+  std::vector<uint32_t> slot_id;             // external id per slot (0xFFFFFFFF = free)
+  std::vector<std::vector<uint32_t>> fwd;    // coordinates of the document in each slot
+  std::vector<uint32_t> free_slots;          // freed columns, reused first
+  uint32_t next_fresh = 0;                   // slots [0, next_fresh) have been used
+  size_t live = 0;
+  uint64_t mutations = 0;
+
+  // buffers
+  snn::DevBuf up, ws, cand, cand2;
+  snn::PinBuf pin;
+  snn::SearchWs last_ws;
+  uint32_t last_nq = 0, last_mode = 0, last_fallbacks = 0;
+  snn::Tune tune;
+  snn::LearnedFilter *filter = nullptr;
+
+  std::string err;
+
+  snn_status fail(snn_status st, const char *fmt, ...);
+  snn_status hip_fail(hipError_t e, const char *what);
+
+  snn_status upload_and_insert(const std::vector<uint32_t> &slots, const std::vector<uint32_t> &ids,
+                               const std::vector<uint64_t> &indptr, const std::vector<uint32_t> &coords,
+                               const std::vector<float> &vals, size_t r0, size_t r1);
+  snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
+                               const std::vector<uint32_t> &co, int clear_bits, int clear_live);
+  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, snn::SearchWs &w);
+  uint32_t merge_fanin(uint32_t k) const;
+  snn_status enqueue_merge(const snn::SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
+                           uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids, float *res_scores,
+                           uint32_t *res_cnt, hipStream_t s);
+  snn_status run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
+                        uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s,
+                        const uint32_t *d_thr_init);
+  snn_status search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
+                            const float *d_v, uint32_t k, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt,
+                            hipStream_t s);
+  void tune_init();
+  void release_extras();
+};

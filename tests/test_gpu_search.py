@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import gen
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    import paper_2301_10622_amd as P
+
+    return P
+
+
+@pytest.fixture(scope="module")
+def small():
+    """The small workload: 10k docs, dim 1,000, m = 32, h = 1, 100 queries of nnz 20."""
+    P = _lib()
+    w = gen.make_small(0)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
+    P.load_docs(ix, w.docs)
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    return w, ix, ora
+
+
+def test_bucket_table_matches_oracle(small):
+    w, ix, _ = small
+    assert np.array_equal(ix.bucket_table(), O.bucket_table(w.hash_seed, w.h, w.n, w.m))
+
+
+def test_bucket_table_h3_matches_oracle():
+    P = _lib()
+    ix = P.Index(5000, 48, 3, capacity=100, hash_seed=77)
+    assert np.array_equal(ix.bucket_table(), O.bucket_table(77, 3, 5000, 48))
+
+
+def test_sketch_columns_bit_exact(small):
+    w, ix, _ = small
+    rng = np.random.default_rng(0)
+    for i in rng.choice(w.docs.rows, 200, replace=False):
+        c, v = w.docs.row(int(i))
+        u, l = ix.read_sketch(int(i))
+        ou, ol, _ = O.sketch(c, v, w.m, w.h, w.hash_seed)
+        assert np.array_equal(u.astype(np.float64), ou) and np.array_equal(l.astype(np.float64), ol), i
+
+
+def test_search_small_all_queries(small):
+    w, ix, ora = small
+    ids, sc, cnt = ix.search_batch(w.queries.indptr, w.queries.coords, w.queries.vals, 10)
+    parity.check_batch(ids, sc, cnt, ora, w.queries, 10, what="small")
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_search_dev_modes_match_host_batch(small, mode):
+    import torch
+
+    P = _lib()
+    w, ix, ora = small
+    dev = torch.device("cuda:0")
+    ip = torch.tensor(w.queries.indptr, dtype=torch.int64, device=dev)
+    qc = torch.tensor(w.queries.coords.astype(np.int32), device=dev)
+    qv = torch.tensor(w.queries.vals, device=dev)
+    ids, sc, cnt = ix.search_batch_dev(ip, qc, qv, 10, mode=mode)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy().astype(np.uint32)
+    sc = sc.cpu().numpy()
+    cnt = cnt.cpu().numpy()
+    hid, hsc, hcnt = ix.search_batch(w.queries.indptr, w.queries.coords, w.queries.vals, 10)
+    # same kernels, same per-document accumulation order: bit-identical
+    assert np.array_equal(cnt, hcnt) and np.array_equal(ids, hid) and np.array_equal(sc, hsc)
+
+
+@pytest.mark.parametrize("k", [1, 7, 100, 1000])
+def test_search_small_various_k(small, k):
+    w, ix, ora = small
+    q = w.queries.take(range(0, 100, 9))
+    ids, sc, cnt = ix.search_batch(q.indptr, q.coords, q.vals, k)
+    parity.check_batch(ids, sc, cnt, ora, q, k, what="k=%d" % k)
+
+
+def test_single_search_equals_batch_row(small):
+    w, ix, _ = small
+    qc, qv = w.queries.row(3)
+    a_ids, a_sc = ix.search(qc, qv, 10)
+    ids, sc, cnt = ix.search_batch(w.queries.indptr, w.queries.coords, w.queries.vals, 10)
+    assert np.array_equal(a_ids, ids[3][: cnt[3]]) and np.array_equal(a_sc, sc[3][: cnt[3]])
+
+
+def _fresh(n, m, h, cap, seed=0):
+    P = _lib()
+    return P.Index(n, m, h, capacity=cap, hash_seed=seed)
+
+
+def test_multi_tile_ragged_signed_h2():
+    """40,123 docs over several tiles with a ragged tail; h = 2; signed values."""
+    P = _lib()
+    rng = np.random.default_rng(1)
+    docs = gen.sparse_rows(11, 40123, 2000, 1.1, rng.integers(1, 80, 40123), "normal")
+    qs = gen.sparse_rows(12, 24, 2000, 1.1, rng.integers(1, 60, 24), "normal")
+    ix = _fresh(2000, 24, 2, 40123, seed=3)
+    P.load_docs(ix, docs)
+    ora = O.Index(docs, 2000, 24, 2, 3)
+    for k in (10, 100):
+        ids, sc, cnt = ix.search_batch(qs.indptr, qs.coords, qs.vals, k)
+        parity.check_batch(ids, sc, cnt, ora, qs, k, what="ragged h2 k=%d" % k)
+
+
+def test_nonnegative_h3_upper_bound_path():
+    P = _lib()
+    rng = np.random.default_rng(2)
+    docs = gen.sparse_rows(21, 20000, 3000, 1.05, rng.integers(5, 120, 20000), "exp")
+    qs = gen.sparse_rows(22, 16, 3000, 1.05, rng.integers(5, 60, 16), "exp")
+    ix = _fresh(3000, 64, 3, 20000, seed=9)
+    P.load_docs(ix, docs)
+    ora = O.Index(docs, 3000, 64, 3, 9)
+    ids, sc, cnt = ix.search_batch(qs.indptr, qs.coords, qs.vals, 50)
+    parity.check_batch(ids, sc, cnt, ora, qs, 50, what="nonneg h3")
+
+
+def test_empty_index_and_k_above_live():
+    P = _lib()
+    ix = _fresh(100, 8, 1, 1000)
+    ids, sc = ix.search(np.array([1, 2]), np.array([1.0, -1.0]), 5)
+    assert len(ids) == 0
+    ix.insert(7, [1, 5], [2.0, 3.0])
+    ix.insert(3, [2], [1.5])
+    ids, sc = ix.search(np.array([1, 2]), np.array([1.0, -1.0]), 5)
+    # doc 7: 1*2 = 2 (no collision possible beyond its own coords in its sketch);
+    # doc 3: -1 * lower bound of coordinate 2 = -1.5
+    assert list(ids) == [7, 3]
+    assert sc[0] >= 2.0 and sc[1] <= -1.5 + 1e-6
+
+
+def test_untouched_documents_score_zero_and_ties_go_to_lower_id():
+    P = _lib()
+    ix = _fresh(50, 8, 1, 100)
+    # five identical documents (identical scores) with shuffled ids, plus untouched ones
+    for i in (40, 12, 33, 5, 27):
+        ix.insert(i, [1, 2, 3], [0.5, -1.0, 2.0])
+    for i in (90, 80, 70):
+        ix.insert(i, [10], [1.0])
+    ids, sc = ix.search(np.array([1, 3]), np.array([1.0, 1.0]), 8)
+    assert list(ids[:5]) == [5, 12, 27, 33, 40]
+    assert np.all(sc[:5] == sc[0]) and list(ids[5:]) == [70, 80, 90] and np.all(sc[5:] == 0)
+    # a query with no non-zero value: every document scores 0, lowest ids first
+    ids, sc = ix.search(np.array([4]), np.array([0.0]), 4)
+    assert list(ids) == [5, 12, 27, 33] and np.all(sc == 0)
+
+
+def test_malformed_inputs_are_rejected():
+    P = _lib()
+    ix = _fresh(100, 8, 1, 100)
+    ix.insert(1, [1, 2], [1.0, 2.0])
+    for c, v in (([100], [1.0]), ([1, 1], [1.0, 2.0]), ([3], [np.nan]), ([3], [np.inf])):
+        with pytest.raises(P.SnnError) as e:
+            ix.search(np.array(c), np.array(v, dtype=np.float32), 3)
+        assert e.value.status == -1
+        with pytest.raises(P.SnnError):
+            ix.insert(2, c, v)
+    with pytest.raises(P.SnnError) as e:
+        ix.insert(1, [3], [1.0])
+    assert e.value.status == -2
+    with pytest.raises(P.SnnError) as e:
+        ix.delete(99)
+    assert e.value.status == -3
+    with pytest.raises(P.SnnError) as e:
+        ix.search(np.array([1]), np.array([1.0]), 0)
+    assert e.value.status == -1
+    assert ix.live_count == 1
+
+
+def test_capacity_full():
+    P = _lib()
+    ix = _fresh(10, 4, 1, 3)  # rounded up to one full tile internally
+    n = 16384
+    ix.insert_batch(np.arange(n), np.arange(n + 1), np.zeros(n), np.ones(n))
+    with pytest.raises(P.SnnError) as e:
+        ix.insert(n, [1], [1.0])
+    assert e.value.status == -4
+    ix.delete(5)
+    ix.insert(n, [1], [1.0])  # reuses the freed slot
+
+
+def test_streaming_history_equals_fresh_index():
+    """Inserts, deletes and re-inserts with slot reuse give the same results as an
+    index built from scratch on the live set."""
+    P = _lib()
+    rng = np.random.default_rng(5)
+    pool = gen.sparse_rows(31, 30000, 1000, 1.1, rng.integers(20, 61, 30000), "normal")
+    qs = gen.sparse_rows(32, 20, 1000, 1.1, np.full(20, 20), "normal")
+    ix = _fresh(1000, 32, 1, 20000, seed=4)
+    live = {}
+    next_doc = 0
+    # bulk load 12k, then a random history of deletes and inserts
+    P.load_docs(ix, pool.take(range(12000)), ids=np.arange(12000, dtype=np.uint32) * 3 + 1)
+    for i in range(12000):
+        live[i * 3 + 1] = i
+    next_doc = 12000
+    for step in range(6):
+        dels = rng.choice(sorted(live), 1500, replace=False)
+        ix.delete_batch(dels)
+        for d in dels:
+            del live[int(d)]
+        new_ids = np.arange(2000) + 100000 + step * 5000
+        rows = np.arange(next_doc, next_doc + 2000)
+        next_doc += 2000
+        sub = pool.take(rows)
+        ix.insert_batch(new_ids, sub.indptr, sub.coords, sub.vals)
+        for i, r in zip(new_ids, rows):
+            live[int(i)] = int(r)
+        # re-insert a few deleted ids with new vectors
+        back = dels[:200]
+        rows = np.arange(next_doc, next_doc + 200)
+        next_doc += 200
+        sub = pool.take(rows)
+        ix.insert_batch(back, sub.indptr, sub.coords, sub.vals)
+        for i, r in zip(back, rows):
+            live[int(i)] = int(r)
+    assert ix.live_count == len(live)
+    lid = np.array(sorted(live), dtype=np.uint32)
+    docs_live = pool.take([live[int(i)] for i in lid])
+    ora = O.Index(docs_live, 1000, 32, 1, 4, ids=lid)
+    ids, sc, cnt = ix.search_batch(qs.indptr, qs.coords, qs.vals, 25)
+    parity.check_batch(ids, sc, cnt, ora, qs, 25, what="streaming")
+    # sketches of re-inserted ids hold the new vectors
+    for i in lid[:50]:
+        c, v = pool.row(live[int(i)])
+        u, l = ix.read_sketch(int(i))
+        ou, ol, _ = O.sketch(c, v, 32, 1, 4)
+        assert np.array_equal(u.astype(np.float64), ou) and np.array_equal(l.astype(np.float64), ol)
