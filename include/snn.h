@@ -122,15 +122,17 @@ typedef enum {
 
 /* Device-pointer batch search. indptr (nq + 1 uint64), coords, vals, and the
  * outputs out_ids (nq x k uint32), out_scores (nq x k float32), out_counts (nq
- * uint32) live in device memory. Enqueued on `stream` (NULL: the index
- * stream); the call does not wait for completion except in
+ * uint32) live in device memory; `total` must equal indptr[nq] (the entry
+ * count, known to the caller, so the call never reads device memory back).
+ * Enqueued on `stream` (NULL: the index stream); the call does not wait for
+ * completion except in
  * SNN_MODE_LEARNED, which reads the fallback flags back on the host and
  * re-runs the queries that need the plain path. Malformed queries produce a
  * count of 0 and set the bit in the status returned by snn_last_batch_status.
  * Errors: SNN_E_INVALID (k = 0, nq = 0, mode unknown, no trained filter for
  * SNN_MODE_LEARNED), SNN_E_NOMEM, SNN_E_DEVICE. */
-snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
-                                const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
+snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
                                 float *out_scores, uint32_t *out_counts, void *stream);
 
 /* Number of queries of the last snn_search_batch_dev call that were malformed
@@ -143,6 +145,14 @@ snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint3
  * live id. Host pointers. */
 snn_status snn_bucket_table(snn_index *ix, uint32_t *out);
 snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l);
+
+/* Kernel timing for measurement. While enabled, every launch of the scoring
+ * and selection kernel is bracketed by HIP events recorded on the stream it is
+ * launched on. snn_profile_read synchronises those events and returns the
+ * summed kernel time in milliseconds and the number of launches since the
+ * previous read (then resets both). */
+snn_status snn_profile_enable(snn_index *ix, int on);
+snn_status snn_profile_read(snn_index *ix, double *tile_ms, uint32_t *launches);
 
 size_t snn_live_count(const snn_index *ix);
 const char *snn_last_error(const snn_index *ix); /* never NULL */

@@ -30,7 +30,7 @@ MODE_PLAIN, MODE_BATCHED, MODE_LEARNED = 0, 1, 2
 EXPORTS = [
     "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
     "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
-    "snn_read_sketch", "snn_live_count", "snn_last_error",
+    "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
 ]
 
 
@@ -66,17 +66,19 @@ def lib():
         L.snn_delete_batch.argtypes = [P, u32, P]
         L.snn_search.argtypes = [P, u32, P, P, u32, P, P, P]
         L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
-        L.snn_search_batch_dev.argtypes = [P, u32, P, P, P, u32, u32, P, P, P, P]
+        L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
         L.snn_bucket_table.argtypes = [P, P]
         L.snn_read_sketch.argtypes = [P, u32, P, P]
+        L.snn_profile_enable.argtypes = [P, i32]
+        L.snn_profile_read.argtypes = [P, P, P]
         L.snn_live_count.argtypes = [P]
         L.snn_live_count.restype = sz
         L.snn_last_error.argtypes = [P]
         L.snn_last_error.restype = ctypes.c_char_p
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
-                     "snn_read_sketch"):
+                     "snn_read_sketch", "snn_profile_enable", "snn_profile_read"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -173,9 +175,13 @@ class Index:
         self._check(lib().snn_search_batch(self._h, nq, _p(ip), _p(c), _p(v), k, _p(ids), _p(sc), _p(cnt)))
         return ids, sc, cnt
 
-    def search_batch_dev(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, out=None, stream=None):
-        """Device tensors in, device tensors out (ids, scores, counts); enqueued on `stream`."""
+    def search_batch_dev(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, out=None, stream=None,
+                         total: Optional[int] = None):
+        """Device tensors in, device tensors out (ids, scores, counts); enqueued on `stream`.
+        `total` = indptr[-1] (read from the tensors when not given)."""
         nq = indptr.numel() - 1
+        if total is None:
+            total = int(coords.numel())
         dev = indptr.device
         if out is None:
             out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
@@ -185,7 +191,7 @@ class Index:
         assert indptr.dtype == torch.int64 and coords.dtype == torch.int32 and vals.dtype == torch.float32
         assert indptr.is_contiguous() and coords.is_contiguous() and vals.is_contiguous()
         assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
-        self._check(lib().snn_search_batch_dev(self._h, nq, _tp(indptr), _tp(coords), _tp(vals), k, mode,
+        self._check(lib().snn_search_batch_dev(self._h, nq, _tp(indptr), int(total), _tp(coords), _tp(vals), k, mode,
                                                _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
         return ids, sc, cnt
 
@@ -194,6 +200,17 @@ class Index:
         fb = ctypes.c_uint32()
         self._check(lib().snn_last_batch_status(self._h, ctypes.byref(inv), ctypes.byref(fb)))
         return int(inv.value), int(fb.value)
+
+    # ------------------------------------------------------------- timing
+    def profile(self, on: bool = True):
+        self._check(lib().snn_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(summed scoring-kernel milliseconds, launches) since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_uint32()
+        self._check(lib().snn_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return float(ms.value), int(n.value)
 
     # ------------------------------------------------------------- inspection
     def bucket_table(self) -> np.ndarray:

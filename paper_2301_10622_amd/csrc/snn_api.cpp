@@ -504,20 +504,36 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   if (mode == SNN_MODE_PLAIN) {
     for (uint32_t q = 0; q < nq; ++q) {
       a.q0 = q;
+      hipEvent_t e0 = prof_on ? prof_event() : nullptr;
+      if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
       HIP_TRY(this, launch_tiles(a, R, 1, s), "tile kernel");
+      if (e0) {
+        hipEvent_t e1 = prof_event();
+        HIP_TRY(this, hipEventRecord(e1, s), "event");
+        prof_events.push_back(e0);
+        prof_events.push_back(e1);
+      }
       st = enqueue_merge(w, nq, q, 1, tiles, k, nullptr, nullptr, d_ids, d_sc, d_cnt, s);
       if (st != SNN_OK) return st;
     }
   } else {
     a.q0 = 0;
+    hipEvent_t e0 = prof_on ? prof_event() : nullptr;
+    if (tune.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
+    if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
     if (tune.persistent) {
-      HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
       HIP_TRY(this, launch_tiles_persistent(a, R, tune.grid, s), "persistent tile kernel");
     } else {
       for (uint32_t c0 = 0; c0 < nq; c0 += kMaxGridY) {
         a.q0 = c0;
         HIP_TRY(this, launch_tiles(a, R, std::min<uint32_t>(kMaxGridY, nq - c0), s), "tile kernel");
       }
+    }
+    if (e0) {
+      hipEvent_t e1 = prof_event();
+      HIP_TRY(this, hipEventRecord(e1, s), "event");
+      prof_events.push_back(e0);
+      prof_events.push_back(e1);
     }
     st = enqueue_merge(w, nq, 0, nq, tiles, k, nullptr, d_thr_init ? w.keff : nullptr, d_ids, d_sc, d_cnt, s);
     if (st != SNN_OK) return st;
@@ -583,21 +599,21 @@ extern "C" snn_status snn_search(snn_index *ix, uint32_t nnz, const uint32_t *co
   return snn_search_batch(ix, 1, ip, coords, vals, k, out_ids, out_scores, out_count);
 }
 
-extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
-                                           const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
-                                           float *out_scores, uint32_t *out_counts, void *stream) {
+extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                           const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode,
+                                           uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream) {
   if (!ix) return SNN_E_INVALID;
   if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
   if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
   if (mode > SNN_MODE_LEARNED) return ix->fail(SNN_E_INVALID, "search: unknown mode %u", mode);
+  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
+    return ix->fail(SNN_E_INVALID, "search: null pointer");
   hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
-  uint64_t last = 0;
-  HIP_TRY(ix, hipMemcpyAsync(&last, indptr + nq, 8, hipMemcpyDeviceToHost, s), "indptr readback");
-  HIP_TRY(ix, hipStreamSynchronize(s), "indptr sync");
   ix->last_nq = nq;
   ix->last_mode = mode;
-  if (mode == SNN_MODE_LEARNED) return ix->search_learned(nq, indptr, last, coords, vals, k, out_ids, out_scores, out_counts, s);
-  return ix->run_search(nq, indptr, last, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, nullptr);
+  if (mode == SNN_MODE_LEARNED)
+    return ix->search_learned(nq, indptr, total, coords, vals, k, out_ids, out_scores, out_counts, s);
+  return ix->run_search(nq, indptr, total, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, nullptr);
 }
 
 extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {
@@ -627,5 +643,40 @@ extern "C" snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, floa
   HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
   HIP_TRY(ix, hipMemcpy2D(u, 4, ix->dev.U + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "U readback");
   HIP_TRY(ix, hipMemcpy2D(l, 4, ix->dev.L + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "L readback");
+  return SNN_OK;
+}
+
+hipEvent_t snn_index::prof_event() {
+  if (!prof_pool.empty()) {
+    hipEvent_t e = prof_pool.back();
+    prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+extern "C" snn_status snn_profile_enable(snn_index *ix, int on) {
+  if (!ix) return SNN_E_INVALID;
+  ix->prof_on = on != 0;
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_profile_read(snn_index *ix, double *tile_ms, uint32_t *launches) {
+  if (!ix) return SNN_E_INVALID;
+  double total = 0;
+  uint32_t n = 0;
+  for (size_t i = 0; i + 1 < ix->prof_events.size(); i += 2) {
+    HIP_TRY(ix, hipEventSynchronize(ix->prof_events[i + 1]), "event sync");
+    float ms = 0;
+    HIP_TRY(ix, hipEventElapsedTime(&ms, ix->prof_events[i], ix->prof_events[i + 1]), "event time");
+    total += ms;
+    ++n;
+  }
+  for (hipEvent_t e : ix->prof_events) ix->prof_pool.push_back(e);
+  ix->prof_events.clear();
+  if (tile_ms) *tile_ms = total;
+  if (launches) *launches = n;
   return SNN_OK;
 }

@@ -5,7 +5,12 @@ void snn_index::tune_init() {
   tune = snn::Tune{};
 }
 
-void snn_index::release_extras() {}
+void snn_index::release_extras() {
+  for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
+  for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
+  prof_events.clear();
+  prof_pool.clear();
+}
 
 snn_status snn_index::search_learned(uint32_t, const uint64_t *, uint64_t, const uint32_t *, const float *, uint32_t,
                                      uint32_t *, float *, uint32_t *, hipStream_t) {

@@ -73,6 +73,12 @@ struct snn_index {
 
   std::string err;
 
+  // kernel timing (snn_profile_*)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_events;  // pairs (start, end) recorded since the last read
+  std::vector<hipEvent_t> prof_pool;
+  hipEvent_t prof_event();
+
   snn_status fail(snn_status st, const char *fmt, ...);
   snn_status hip_fail(hipError_t e, const char *what);
 
