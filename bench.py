@@ -48,6 +48,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB: run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only (the index is not sharded across GPUs); use --gpus 1",
@@ -62,6 +64,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes))
+        del src, dst
     log("generating workload")
     w = gen.make_splade_like(0, docs=args.docs, queries=args.queries)
     log("docs %d (nnz %d), queries %d (nnz %d)" % (w.docs.rows, w.docs.nnz, w.queries.rows, w.queries.nnz))
