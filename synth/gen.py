@@ -188,9 +188,11 @@ def sparse_rows(seed: int, rows: int, n: int, zipf_s: float, psi: np.ndarray, la
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
     if len(jobs) > 1 and workers > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(min(workers, len(jobs))) as pool:
-            parts = pool.map(_chunk, jobs)
+        # threads, not processes: numpy releases the GIL in the heavy steps, and
+        # forked workers do not mix well with profilers attached to the parent
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(min(workers, len(jobs))) as pool:
+            parts = list(pool.map(_chunk, jobs))
     else:
         parts = [_chunk(j) for j in jobs]
     coords = np.concatenate([p[0] for p in parts]) if parts else np.zeros(0, np.uint32)
