@@ -35,8 +35,8 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
   __syncthreads();
   const uint64_t e0 = indptr[d], e1 = indptr[d + 1];
   const uint32_t slot = slots[d];
-  const uint64_t bit = 1ull << (slot & 63u);
-  const size_t word = slot >> 6;
+  const uint64_t bit = 1ull << slot_bit(slot);
+  const size_t word = slot_word(slot);
   for (uint64_t e = e0 + lane; e < e1; e += 64) {
     const uint32_t j = coords[e];
     const float v = vals[e];
@@ -80,8 +80,8 @@ __global__ __launch_bounds__(64) void k_delete(DevIndex ix, uint32_t n, const ui
   const uint32_t d = blockIdx.x;
   if (d >= n) return;
   const uint32_t slot = slots[d];
-  const uint64_t mask = ~(1ull << (slot & 63u));
-  const size_t word = slot >> 6;
+  const uint64_t mask = ~(1ull << slot_bit(slot));
+  const size_t word = slot_word(slot);
   if (clear_bits)
     for (uint64_t e = indptr[d] + threadIdx.x; e < indptr[d + 1]; e += 64)
       atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + word], (unsigned long long)mask);

@@ -3,15 +3,17 @@
 // top-k (Alg. 3 / Alg. 7 with k' = k).
 //
 // A workgroup owns one (query, doc tile) pair. The tile is 256 * R consecutive
-// slots: wave w, lane l, register r owns slot tile0 + 64 * (w * R + r) + l.
-// For each query coordinate j, in the order of Alg. 6, the wave reads the R
-// posting-bitmap words of its slots; each word is used directly as the
-// wavefront lane mask (inverse ballot), and every lane whose bit is set reads
-// its document's bound from sketch row pi(j) -- min over the U rows if q_j > 0,
-// max over the L rows otherwise -- and adds q_j * bound to its private
-// accumulator. A lane whose bit is clear loads from an out-of-range buffer
-// offset, which returns 0 without touching memory, so the add is an exact
-// no-op and the inner loop has no branches. Scores never leave registers.
+// slots, R / 4 groups of 256 per wave; in a group lane l owns the 4 adjacent
+// slots 4l .. 4l+3. For each query coordinate j, in the order of Alg. 6, the
+// wave reads the 4 posting-bitmap words of each of its groups; word i holds
+// bit l for slot 4l + i, so each word is directly a wavefront lane mask
+// (inverse ballot). A lane with any of its 4 slots on the list reads their 4
+// bounds from sketch row pi(j) -- min over the U rows if q_j > 0, max over the
+// L rows otherwise -- with one 16-byte load, and adds q_j * bound for the
+// slots whose bit is set. A lane with none loads from an out-of-range buffer
+// offset, which returns 0 without touching memory, so the inner loop has no
+// branches and one vector memory instruction serves 256 slots. Scores never
+// leave registers.
 //
 // Selection keys are ord(score) << 32 | (0xFFFFFFFF - id), so a larger key
 // means a higher score, then a lower id. The tile first finds the k-th largest
@@ -99,11 +101,20 @@ __device__ __forceinline__ uint32_t count_pred(const bool (&p)[R]) {
   return c;
 }
 
+// Slot layout inside a 256-slot group (see snn_device.h): lane l owns slots
+// 4l .. 4l+3; bitmap word i of the group has bit l set when slot 4l + i is
+// present. Register index x = 4r + i of a lane is slot wslot0 + 256r + 4l + i.
+template <int R>
+__device__ __forceinline__ uint32_t slot_of(uint32_t wslot0, int x, int lane) {
+  return wslot0 + 256u * (uint32_t)(x >> 2) + 4u * (uint32_t)lane + (uint32_t)(x & 3);
+}
+
 template <int R>
 __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
+  constexpr int G = R / 4;  // 256-slot groups per wave
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 64u * R;
+  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
   const uint32_t wword0 = wslot0 >> 6;
   const DevIndex &ix = a.ix;
   const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
@@ -116,9 +127,13 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   }
 
   // ---------------- scoring (Alg. 6) ----------------
+  // For each group the lane loads its 4 slots' bounds with one 16-byte load
+  // (out of range, so zeros and no memory traffic, when none of them is on the
+  // list) and adds q_j * bound for the slots whose bit is set; absent slots add
+  // q_j * 0 or 0 * (finite stale bound), an exact no-op.
   float acc[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = 0.0f;
+  for (int x = 0; x < R; ++x) acc[x] = 0.0f;
 
   const uint64_t e0 = as_const(a.qd.qptr)[q];
   const uint32_t ne = as_const(a.qd.cnt)[q];
@@ -135,34 +150,52 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
     if (h == 1) {
       const __amdgpu_buffer_rsrc_t rs =
-          __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, R * 64 * 4, kBufFlags);
+          __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const bool on = __builtin_amdgcn_inverse_ballot_w64(wp[r]);
-        const int off = on ? (r * 64 + lane) * 4 : kOob;
-        const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-        acc[r] = __builtin_fmaf(qv, v, acc[r]);
+      for (int r = 0; r < G; ++r) {
+        const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
+        const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
+        const int off = any ? r * 1024 + lane * 16 : kOob;
+        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0));
+        const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
+        const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0));
+        acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v0, acc[4 * r + 0]);
+        acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v1, acc[4 * r + 1]);
+        acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v2, acc[4 * r + 2]);
+        acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v3, acc[4 * r + 3]);
       }
     } else {
-      // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows
+      // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows;
+      // unused mappings repeat row 0, which leaves the min / max unchanged
       const bool upper = qv > 0.0f;
-      __amdgpu_buffer_rsrc_t rs0, rs1, rs2, rs3;
-      rs0 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h] * cap), 0, R * 256, kBufFlags);
-      rs1 = rs2 = rs3 = rs0;
-      if (h > 1) rs1 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 1] * cap), 0, R * 256, kBufFlags);
-      if (h > 2) rs2 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 2] * cap), 0, R * 256, kBufFlags);
-      if (h > 3) rs3 = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + 3] * cap), 0, R * 256, kBufFlags);
+      __amdgpu_buffer_rsrc_t rs[4];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const bool on = __builtin_amdgcn_inverse_ballot_w64(wp[r]);
-        const int off = on ? (r * 64 + lane) * 4 : kOob;
-        // unused mappings repeat row 0, which leaves the min/max unchanged
-        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs0, off, 0, 0));
-        const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs1, off, 0, 0));
-        const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs2, off, 0, 0));
-        const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs3, off, 0, 0));
-        const float v = upper ? fminf(fminf(v0, v1), fminf(v2, v3)) : fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
-        acc[r] = __builtin_fmaf(qv, v, acc[r]);
+      for (int o = 0; o < 4; ++o) {
+        const uint32_t oo = (uint32_t)o < h ? (uint32_t)o : 0u;
+        rs[o] = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + oo] * cap), 0, G * 1024,
+                                                  kBufFlags);
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
+        const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
+        const int off = any ? r * 1024 + lane * 16 : kOob;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[0], off + 4 * i, 0, 0));
+#pragma unroll
+        for (int o = 1; o < 4; ++o) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[o], off + 4 * i, 0, 0));
+            v[i] = upper ? __builtin_fminf(v[i], x) : __builtin_fmaxf(v[i], x);
+          }
+        }
+        acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v[0], acc[4 * r + 0]);
+        acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v[1], acc[4 * r + 1]);
+        acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v[2], acc[4 * r + 2]);
+        acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v[3], acc[4 * r + 3]);
       }
     }
   }
@@ -173,11 +206,11 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   const uint32_t thr0 = __hip_atomic_load(&a.thr[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const uint32_t thr = __builtin_amdgcn_readfirstlane(thr0);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const bool lv = __builtin_amdgcn_inverse_ballot_w64(lw[r]);
-    const float s = acc[r] == 0.0f ? 0.0f : acc[r];  // -0 -> +0
+  for (int x = 0; x < R; ++x) {
+    const bool lv = __builtin_amdgcn_inverse_ballot_w64(lw[x]);  // word 4r + i <-> register 4r + i
+    const float s = acc[x] == 0.0f ? 0.0f : acc[x];  // -0 -> +0
     const uint32_t kk = ord_key(s);
-    key[r] = (lv && kk >= thr) ? kk : 0u;
+    key[x] = (lv && kk >= thr) ? kk : 0u;
   }
   int par = 0;
   uint32_t nvalid;
@@ -209,7 +242,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
         // ties at the k-th score: keep the `need` lowest ids among them
 #pragma unroll
         for (int r = 0; r < R; ++r)
-          idk[r] = key[r] == T ? (0xFFFFFFFFu - ix.slot2id[wslot0 + r * 64 + lane]) : 0u;
+          idk[r] = key[r] == T ? (0xFFFFFFFFu - ix.slot2id[slot_of<R>(wslot0, r, lane)]) : 0u;
         bool ex2;
         uint32_t need2;
         T2 = select_kth<R>(idk, need, sh, par, ex2, need2);
@@ -233,7 +266,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     if (e) {
       const uint32_t pos = basepos + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      const uint32_t id = ix.slot2id[wslot0 + r * 64 + lane];
+      const uint32_t id = ix.slot2id[slot_of<R>(wslot0, r, lane)];
       cout[pos] = ((uint64_t)key[r] << 32) | (uint64_t)(0xFFFFFFFFu - id);
     }
   }

@@ -11,10 +11,11 @@
 //   slot2id  uint32 [cap]         external id of the document in each slot
 //   bucket   uint32 [h][dim]      the random mappings pi_o(j)
 //
-// One 64-bit bitmap word covers 64 consecutive slots, which is exactly one
-// wavefront of 64 lanes: lane l owns slot 64*w + l, so the word is the wave's
-// execution mask for that coordinate and no lane ever contends with another
-// for a score.
+// Bitmaps are interleaved in groups of 256 slots so that a 64-bit word is a
+// wavefront lane mask while each lane still reads 4 adjacent sketch values at
+// once: in group g (slots 256g .. 256g+255), word 4g + i has bit l set for slot
+// 256g + 4l + i. Lane l of a wave owns slots 4l .. 4l+3 of each of its groups,
+// so no lane ever contends with another for a score.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -84,6 +85,9 @@ struct MergeArgs {
   uint32_t *fallback;   // [nq] set to 1 when fewer than keff candidates survived
   const uint32_t *status; // [nq] malformed queries produce 0 results
 };
+
+__host__ __device__ inline uint32_t slot_word(uint32_t slot) { return ((slot >> 8) << 2) | (slot & 3u); }
+__host__ __device__ inline uint32_t slot_bit(uint32_t slot) { return (slot >> 2) & 63u; }
 
 // order-preserving float -> uint32 map (negative floats reversed); 0 never occurs for finite x
 __host__ __device__ inline uint32_t ord_key(float x) {
