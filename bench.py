@@ -124,6 +124,10 @@ def main():
                "tile_kernel_ms_per_launch": kms / max(launches, 1), "tile_launches_per_step": launches / steps}
         return res, out
 
+    log("autotuning the schedule on the batch")
+    sched = ix.autotune(ip, qc, qv, args.k, total=total)
+    log("schedule: %s" % sched)
+
     forms = {}
     outs = {}
     for name in args.forms.split(","):
@@ -163,6 +167,7 @@ def main():
         "roofline": roofline,
         "forms": {n: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()} for n, r in forms.items()},
         "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1),
+        "schedule": sched,
     }
 
     # ---------------------------------------------------------------- oracle

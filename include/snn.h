@@ -140,6 +140,31 @@ snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indp
  * back to the plain path. */
 snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks);
 
+/* Launch schedule of the search kernels. R is the number of slots each lane
+ * scores (a workgroup of 256 lanes covers a tile of 256 * R slots); grid is the
+ * workgroup count of the persistent batched kernel; persistent = 0 launches one
+ * workgroup per (query, tile) instead. */
+typedef struct {
+  int32_t R_plain;
+  int32_t R_batch;
+  uint32_t grid;
+  uint32_t persistent;
+  float best_ms;      /* tuned batched pass, ms (0 if not tuned) */
+  float default_ms;   /* same batch with the default schedule, ms */
+  uint32_t tried;     /* candidate schedules timed */
+} snn_schedule;
+
+/* Autotuner: time the candidate schedules (R in {16, 32, 64}; persistent grids
+ * of 1024, 2048 and 4096 workgroups or one workgroup per item) on the given
+ * device-resident batch, keep the fastest for later searches of this index,
+ * and report it in *out (may be NULL). Same arguments as snn_search_batch_dev
+ * without the mode; scratch outputs are allocated internally. Blocking. */
+snn_status snn_autotune(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total, const uint32_t *coords,
+                        const float *vals, uint32_t k, snn_schedule *out);
+/* Read or set the schedule (set ignores best_ms, default_ms, tried). */
+snn_status snn_get_schedule(snn_index *ix, snn_schedule *out);
+snn_status snn_set_schedule(snn_index *ix, const snn_schedule *in);
+
 /* Read back state for tests: the bucket table pi_o(j) as h x dim uint32
  * (row-major), and the stored sketch column (m floats each for U and L) of a
  * live id. Host pointers. */

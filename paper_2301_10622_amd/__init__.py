@@ -31,6 +31,7 @@ EXPORTS = [
     "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
     "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
+    "snn_autotune", "snn_get_schedule", "snn_set_schedule",
 ]
 
 
@@ -38,6 +39,15 @@ class SnnError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__("%s: %s" % (STATUS.get(status, str(status)), msg))
         self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("R_plain", ctypes.c_int32), ("R_batch", ctypes.c_int32), ("grid", ctypes.c_uint32),
+                ("persistent", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
+                ("tried", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Config(ctypes.Structure):
@@ -72,13 +82,17 @@ def lib():
         L.snn_read_sketch.argtypes = [P, u32, P, P]
         L.snn_profile_enable.argtypes = [P, i32]
         L.snn_profile_read.argtypes = [P, P, P]
+        L.snn_autotune.argtypes = [P, u32, P, u64, P, P, u32, P]
+        L.snn_get_schedule.argtypes = [P, P]
+        L.snn_set_schedule.argtypes = [P, P]
         L.snn_live_count.argtypes = [P]
         L.snn_live_count.restype = sz
         L.snn_last_error.argtypes = [P]
         L.snn_last_error.restype = ctypes.c_char_p
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
-                     "snn_read_sketch", "snn_profile_enable", "snn_profile_read"):
+                     "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
+                     "snn_get_schedule", "snn_set_schedule"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -211,6 +225,25 @@ class Index:
         n = ctypes.c_uint32()
         self._check(lib().snn_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+    # ------------------------------------------------------------- schedule
+    def autotune(self, indptr, coords, vals, k: int, total: Optional[int] = None) -> dict:
+        """Time candidate schedules on a device-resident batch and keep the fastest."""
+        nq = indptr.numel() - 1
+        total = int(coords.numel()) if total is None else int(total)
+        sch = Schedule()
+        self._check(lib().snn_autotune(self._h, nq, _tp(indptr), total, _tp(coords), _tp(vals), k,
+                                       ctypes.byref(sch)))
+        return sch.as_dict()
+
+    def schedule(self) -> dict:
+        sch = Schedule()
+        self._check(lib().snn_get_schedule(self._h, ctypes.byref(sch)))
+        return sch.as_dict()
+
+    def set_schedule(self, R_plain=16, R_batch=32, grid=2048, persistent=True):
+        sch = Schedule(R_plain, R_batch, grid, 1 if persistent else 0, 0.0, 0.0, 0)
+        self._check(lib().snn_set_schedule(self._h, ctypes.byref(sch)))
 
     # ------------------------------------------------------------- inspection
     def bucket_table(self) -> np.ndarray:

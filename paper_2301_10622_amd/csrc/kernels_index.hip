@@ -108,6 +108,19 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
   return hipGetLastError();
 }
 
+__global__ void k_copy_u32(uint32_t *d, const uint32_t *s, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint32_t blocks = (uint32_t)((n + 255) / 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_copy_u32, dim3(blocks), dim3(256), 0, s, dst, src, n);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Query preparation (Alg. 6, first steps). One workgroup per query:
 //   drop zero values (nz), reject coordinates >= dim, non-finite values and

@@ -468,75 +468,149 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32
   return SNN_OK;
 }
 
-snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
-                                 const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
-                                 uint32_t *d_cnt, hipStream_t s, const uint32_t *d_thr_init) {
-  const int R = mode == SNN_MODE_PLAIN ? tune.R_plain : tune.R_batch;
-  const uint32_t tile_docs = (uint32_t)kBlock * R;
-  const uint32_t tiles = (next_fresh + tile_docs - 1) / tile_docs;
-  if (tiles == 0) {
-    HIP_TRY(this, launch_fill_u32(d_cnt, 0u, nq, s), "fill");
-    return SNN_OK;
-  }
-  SearchWs w;
-  snn_status st = prepare_workspace(nq, total, k, tiles, w);
-  if (st != SNN_OK) return st;
-  last_ws = w;
-  QueryDesc qd{d_ptr, w.cnt, w.status, w.j, w.q, w.b};
-  HIP_TRY(this, launch_prep(dev, qd, nq, d_c, d_v, s), "prep kernel");
-  if (d_thr_init) {
-    HIP_TRY(this, hipMemcpyAsync(w.thr, d_thr_init, (size_t)nq * 4, hipMemcpyDeviceToDevice, s), "thr init");
+// Enqueue one batched or plain search. The device work is: query preparation,
+// threshold initialisation, the scoring + selection tiles, the merge levels.
+snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t ev0,
+                                     hipEvent_t ev1) {
+  const SearchWs &w = p.w;
+  QueryDesc qd{p.d_ptr, w.cnt, w.status, w.j, w.q, w.b};
+  HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, s), "prep kernel");
+  if (o.thr_init) {
+    HIP_TRY(this, launch_copy_u32(w.thr, o.thr_init, p.nq, s), "thr init");
   } else {
-    HIP_TRY(this, launch_fill_u32(w.thr, 0u, nq, s), "thr fill");
+    HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
   }
   TileArgs a{};
   a.ix = dev;
   a.qd = qd;
-  a.nq = nq;
-  a.tiles = tiles;
-  a.kmax = k;
-  a.kq = nullptr;
+  a.nq = p.nq;
+  a.tiles = p.tiles;
+  a.kmax = p.k;
+  a.kq = o.kq;
   a.thr = w.thr;
   a.cand = w.cand;
   a.cand_cnt = w.cand_cnt;
   a.queue = w.queue;
   a.xcds = 8;
-  if (mode == SNN_MODE_PLAIN) {
-    for (uint32_t q = 0; q < nq; ++q) {
+  if (p.mode == SNN_MODE_PLAIN) {
+    for (uint32_t q = 0; q < p.nq; ++q) {
       a.q0 = q;
       hipEvent_t e0 = prof_on ? prof_event() : nullptr;
       if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
-      HIP_TRY(this, launch_tiles(a, R, 1, s), "tile kernel");
+      HIP_TRY(this, launch_tiles(a, p.R, 1, s), "tile kernel");
       if (e0) {
         hipEvent_t e1 = prof_event();
         HIP_TRY(this, hipEventRecord(e1, s), "event");
         prof_events.push_back(e0);
         prof_events.push_back(e1);
       }
-      st = enqueue_merge(w, nq, q, 1, tiles, k, nullptr, nullptr, d_ids, d_sc, d_cnt, s);
+      snn_status st = enqueue_merge(w, p.nq, q, 1, p.tiles, p.k, o.kq, o.keff, p.d_ids, p.d_sc, p.d_cnt, s);
       if (st != SNN_OK) return st;
     }
+    return SNN_OK;
+  }
+  a.q0 = 0;
+  if (p.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
+  if (ev0) HIP_TRY(this, hipEventRecord(ev0, s), "event");
+  if (p.persistent) {
+    HIP_TRY(this, launch_tiles_persistent(a, p.R, p.grid, s), "persistent tile kernel");
   } else {
-    a.q0 = 0;
-    hipEvent_t e0 = prof_on ? prof_event() : nullptr;
-    if (tune.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
-    if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
-    if (tune.persistent) {
-      HIP_TRY(this, launch_tiles_persistent(a, R, tune.grid, s), "persistent tile kernel");
-    } else {
-      for (uint32_t c0 = 0; c0 < nq; c0 += kMaxGridY) {
-        a.q0 = c0;
-        HIP_TRY(this, launch_tiles(a, R, std::min<uint32_t>(kMaxGridY, nq - c0), s), "tile kernel");
-      }
+    for (uint32_t c0 = 0; c0 < p.nq; c0 += kMaxGridY) {
+      a.q0 = c0;
+      HIP_TRY(this, launch_tiles(a, p.R, std::min<uint32_t>(kMaxGridY, p.nq - c0), s), "tile kernel");
     }
+  }
+  if (ev1) HIP_TRY(this, hipEventRecord(ev1, s), "event");
+  return enqueue_merge(w, p.nq, 0, p.nq, p.tiles, p.k, o.kq, o.keff, p.d_ids, p.d_sc, p.d_cnt, s);
+}
+
+snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
+                                  const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
+                                  uint32_t *d_cnt, SearchPlan &p) {
+  p.nq = nq;
+  p.d_ptr = d_ptr;
+  p.total = total;
+  p.d_c = d_c;
+  p.d_v = d_v;
+  p.k = k;
+  p.mode = mode;
+  p.d_ids = d_ids;
+  p.d_sc = d_sc;
+  p.d_cnt = d_cnt;
+  p.R = mode == SNN_MODE_PLAIN ? tune.R_plain : tune.R_batch;
+  p.persistent = mode != SNN_MODE_PLAIN && tune.persistent;
+  p.grid = tune.grid;
+  const uint32_t tile_docs = (uint32_t)kBlock * p.R;
+  p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
+  if (p.tiles == 0) return SNN_OK;
+  return prepare_workspace(nq, total, k, p.tiles, p.w);
+}
+
+snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
+                                 const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
+                                 uint32_t *d_cnt, hipStream_t s, const SearchOpts &o) {
+  SearchPlan p;
+  snn_status st = plan_search(nq, d_ptr, total, d_c, d_v, k, mode, d_ids, d_sc, d_cnt, p);
+  if (st != SNN_OK) return st;
+  if (p.tiles == 0) {  // nothing was ever inserted: no results
+    HIP_TRY(this, launch_fill_u32(d_cnt, 0u, nq, s), "fill");
+    return SNN_OK;
+  }
+  last_ws = p.w;
+  if (mode == SNN_MODE_PLAIN || !use_graphs) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof_on && mode != SNN_MODE_PLAIN) {
+      e0 = prof_event();
+      e1 = prof_event();
+    }
+    st = enqueue_search(p, o, s, e0, e1);
     if (e0) {
-      hipEvent_t e1 = prof_event();
-      HIP_TRY(this, hipEventRecord(e1, s), "event");
       prof_events.push_back(e0);
       prof_events.push_back(e1);
     }
-    st = enqueue_merge(w, nq, 0, nq, tiles, k, nullptr, d_thr_init ? w.keff : nullptr, d_ids, d_sc, d_cnt, s);
-    if (st != SNN_OK) return st;
+    return st;
+  }
+  // batched forms replay a captured HIP graph of the whole pass
+  GraphKey key{};
+  key.nq = nq; key.total = total; key.k = k; key.mode = mode; key.R = p.R; key.grid = p.grid;
+  key.persistent = p.persistent; key.tiles = p.tiles; key.prof = prof_on;
+  key.ptr = d_ptr; key.c = d_c; key.v = d_v; key.ids = d_ids; key.sc = d_sc; key.cnt = d_cnt;
+  key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
+  key.ws = ws.p; key.cand = cand.p; key.cand2 = cand2.p;
+  GraphEntry *g = graphs.find(key);
+  if (!g) {
+    GraphEntry e;
+    e.key = key;
+    if (prof_on) {
+      HIP_TRY(this, hipEventCreate(&e.ev0), "event");
+      HIP_TRY(this, hipEventCreate(&e.ev1), "event");
+    }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(this, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
+    snn_status est = enqueue_search(p, o, s, e.ev0, e.ev1);
+    hipError_t ce = hipStreamEndCapture(s, &graph);
+    if (est != SNN_OK || ce != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      e.release();
+      if (est != SNN_OK) return est;
+      return hip_fail(ce, "graph capture");
+    }
+    hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      e.release();
+      return hip_fail(ie, "graph instantiate");
+    }
+    g = graphs.insert(e);
+  }
+  HIP_TRY(this, hipGraphLaunch(g->exec, s), "graph launch");
+  if (prof_on && g->ev1) {
+    // the graph's event nodes are re-recorded by every replay: read them now
+    HIP_TRY(this, hipEventSynchronize(g->ev1), "event sync");
+    float ms = 0;
+    HIP_TRY(this, hipEventElapsedTime(&ms, g->ev0, g->ev1), "event time");
+    prof_accum_ms += ms;
+    prof_accum_n += 1;
   }
   return SNN_OK;
 }
@@ -580,7 +654,7 @@ extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_
   float *d_sc = (float *)(d_ids + (size_t)nq * k);
   uint32_t *d_cnt = (uint32_t *)(d_sc + (size_t)nq * k);
   snn_status st = ix->run_search(nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v), k,
-                                 SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, nullptr);
+                                 SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, SearchOpts{});
   if (st != SNN_OK) return st;
   HIP_TRY(ix, hipMemcpyAsync(hp + o_out, d_ids, out_bytes - 64, hipMemcpyDeviceToHost, s), "search readback");
   HIP_TRY(ix, hipStreamSynchronize(s), "search sync");
@@ -613,7 +687,7 @@ extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uin
   ix->last_mode = mode;
   if (mode == SNN_MODE_LEARNED)
     return ix->search_learned(nq, indptr, total, coords, vals, k, out_ids, out_scores, out_counts, s);
-  return ix->run_search(nq, indptr, total, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, nullptr);
+  return ix->run_search(nq, indptr, total, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, SearchOpts{});
 }
 
 extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {
@@ -676,6 +750,10 @@ extern "C" snn_status snn_profile_read(snn_index *ix, double *tile_ms, uint32_t 
   }
   for (hipEvent_t e : ix->prof_events) ix->prof_pool.push_back(e);
   ix->prof_events.clear();
+  total += ix->prof_accum_ms;
+  n += ix->prof_accum_n;
+  ix->prof_accum_ms = 0;
+  ix->prof_accum_n = 0;
   if (tile_ms) *tile_ms = total;
   if (launches) *launches = n;
   return SNN_OK;

@@ -6,6 +6,7 @@ void snn_index::tune_init() {
 }
 
 void snn_index::release_extras() {
+  graphs.clear();
   for (hipEvent_t e : prof_events) (void)hipEventDestroy(e);
   for (hipEvent_t e : prof_pool) (void)hipEventDestroy(e);
   prof_events.clear();

@@ -46,6 +46,75 @@ struct Tune {
 
 struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
 
+// Optional per-query inputs of a search (device arrays of nq entries).
+struct SearchOpts {
+  const uint32_t *thr_init = nullptr;  // initial inclusive threshold keys (learned filter)
+  const uint32_t *kq = nullptr;        // per-query k (<= the batch k)
+  const uint32_t *keff = nullptr;      // count below which the filter check reports a fallback
+};
+
+struct SearchPlan {
+  uint32_t nq = 0, k = 0, tiles = 0, grid = 0;
+  int mode = 0, R = 16;
+  bool persistent = false;
+  uint64_t total = 0;
+  const uint64_t *d_ptr = nullptr;
+  const uint32_t *d_c = nullptr;
+  const float *d_v = nullptr;
+  uint32_t *d_ids = nullptr, *d_cnt = nullptr;
+  float *d_sc = nullptr;
+  SearchWs w;
+};
+
+struct GraphKey {
+  uint32_t nq, k, mode, R, grid, tiles;
+  uint64_t total;
+  bool persistent, prof;
+  const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2;
+  hipStream_t stream;
+  bool operator==(const GraphKey &o) const {
+    return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
+           total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
+           v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
+           ws == o.ws && cand == o.cand && cand2 == o.cand2 && stream == o.stream;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key{};
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    exec = nullptr;
+    ev0 = ev1 = nullptr;
+  }
+};
+
+// A few instantiated graphs, most recent last.
+struct GraphCache {
+  std::vector<GraphEntry> e;
+  GraphEntry *find(const GraphKey &k) {
+    for (auto &x : e)
+      if (x.key == k) return &x;
+    return nullptr;
+  }
+  GraphEntry *insert(const GraphEntry &g) {
+    if (e.size() >= 8) {
+      e.front().release();
+      e.erase(e.begin());
+    }
+    e.push_back(g);
+    return &e.back();
+  }
+  void clear() {
+    for (auto &x : e) x.release();
+    e.clear();
+  }
+};
+
 }  // namespace snn
 
 struct snn_index {
@@ -73,8 +142,16 @@ struct snn_index {
 
   std::string err;
 
+  snn::GraphCache graphs;
+  bool use_graphs = true;
+  float tune_best_ms = 0, tune_default_ms = 0;
+  uint32_t tune_tried = 0;
+  snn_schedule last_sched{};
+
   // kernel timing (snn_profile_*)
   bool prof_on = false;
+  double prof_accum_ms = 0;
+  uint32_t prof_accum_n = 0;
   std::vector<hipEvent_t> prof_events;  // pairs (start, end) recorded since the last read
   std::vector<hipEvent_t> prof_pool;
   hipEvent_t prof_event();
@@ -92,9 +169,13 @@ struct snn_index {
   snn_status enqueue_merge(const snn::SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
                            uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids, float *res_scores,
                            uint32_t *res_cnt, hipStream_t s);
+  snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
+                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p);
+  snn_status enqueue_search(const snn::SearchPlan &p, const snn::SearchOpts &o, hipStream_t s, hipEvent_t ev0,
+                            hipEvent_t ev1);
   snn_status run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s,
-                        const uint32_t *d_thr_init);
+                        const snn::SearchOpts &o);
   snn_status search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
                             const float *d_v, uint32_t k, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt,
                             hipStream_t s);

@@ -231,3 +231,77 @@ def test_streaming_history_equals_fresh_index():
         u, l = ix.read_sketch(int(i))
         ou, ol, _ = O.sketch(c, v, 32, 1, 4)
         assert np.array_equal(u.astype(np.float64), ou) and np.array_equal(l.astype(np.float64), ol)
+
+
+def _dev_batch(q):
+    import torch
+
+    dev = torch.device("cuda:0")
+    return (torch.tensor(q.indptr, dtype=torch.int64, device=dev),
+            torch.tensor(q.coords.astype(np.int32), device=dev), torch.tensor(q.vals, device=dev))
+
+
+def _dev_search(ix, tensors, k, mode, out=None):
+    import torch
+
+    ids, sc, cnt = ix.search_batch_dev(*tensors, k, mode=mode, out=out)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy().copy(), sc.cpu().numpy().copy(), cnt.cpu().numpy().copy()
+
+
+def test_all_schedules_give_identical_results(small):
+    """Every tile size and launch shape computes the same per-document sums in the
+    same order and the same exact selection: results are bit-identical."""
+    P = _lib()
+    w, ix, ora = small
+    t = _dev_batch(w.queries)
+    ref = _dev_search(ix, t, 10, P.MODE_PLAIN)
+    saved = ix.schedule()
+    try:
+        for R in (16, 32, 64):
+            for persistent, grid in ((True, 1024), (True, 4096), (False, 2048)):
+                ix.set_schedule(R_plain=R, R_batch=R, grid=grid, persistent=persistent)
+                for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
+                    got = _dev_search(ix, t, 10, mode)
+                    for a, b in zip(ref, got):
+                        assert np.array_equal(a, b), (R, persistent, grid, mode)
+    finally:
+        ix.set_schedule(saved["R_plain"], saved["R_batch"], saved["grid"], bool(saved["persistent"]))
+
+
+def test_graph_replays_match_eager_between_mutations():
+    """The batched form replays a captured HIP graph; each replay, with eager work
+    and index mutations in between, equals the eager plain path at that state."""
+    import torch
+
+    P = _lib()
+    w = gen.make_small(3, docs=6000, queries=40)
+    ix = P.Index(w.n, w.m, w.h, capacity=20000, hash_seed=w.hash_seed)
+    P.load_docs(ix, w.docs)
+    t = _dev_batch(w.queries)
+    dev = torch.device("cuda:0")
+    out = (torch.empty((40, 10), dtype=torch.int32, device=dev), torch.empty((40, 10), dtype=torch.float32, device=dev),
+           torch.empty(40, dtype=torch.int32, device=dev))
+    extra = gen.small_docs(99, 400)
+    for it in range(5):
+        plain = _dev_search(ix, t, 10, P.MODE_PLAIN)
+        got = _dev_search(ix, t, 10, P.MODE_BATCHED, out=out)  # same buffers: graph replay after the first
+        for a, b in zip(plain, got):
+            assert np.array_equal(a, b), it
+        # mutate between replays: delete some docs, insert new ones (slot reuse)
+        ix.delete_batch(np.arange(it * 50, it * 50 + 50))
+        sub = extra.take(range(it * 80, it * 80 + 80))
+        ix.insert_batch(np.arange(80) + 100000 + it * 100, sub.indptr, sub.coords, sub.vals)
+
+
+def test_autotune_keeps_results_and_reports_schedule(small):
+    P = _lib()
+    w, ix, ora = small
+    t = _dev_batch(w.queries)
+    before = _dev_search(ix, t, 10, P.MODE_BATCHED)
+    sch = ix.autotune(*t, 10)
+    assert sch["R_batch"] in (16, 32, 64) and sch["R_plain"] in (16, 32, 64) and sch["tried"] == 15
+    assert sch["best_ms"] > 0 and sch["best_ms"] <= sch["default_ms"] * 1.5
+    after = _dev_search(ix, t, 10, P.MODE_BATCHED)
+    for a, b in zip(before, after):
+        assert np.array_equal(a, b)
