@@ -77,7 +77,8 @@ def main():
     w = gen.make_splade_like(0, docs=args.docs, queries=args.queries)
     log("docs %d (nnz %d), queries %d (nnz %d)" % (w.docs.rows, w.docs.nnz, w.queries.rows, w.queries.nnz))
 
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # non-default stream (HIP graphs cannot capture the legacy stream)
+    torch.cuda.set_stream(stream)
     ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream)
     torch.cuda.synchronize()
     t = time.time()

@@ -557,7 +557,8 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
     return SNN_OK;
   }
   last_ws = p.w;
-  if (mode == SNN_MODE_PLAIN || !use_graphs) {
+  // graphs need a capturable stream: the legacy default stream is not one
+  if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof_on && mode != SNN_MODE_PLAIN) {
       e0 = prof_event();

@@ -276,7 +276,9 @@ def test_graph_replays_match_eager_between_mutations():
 
     P = _lib()
     w = gen.make_small(3, docs=6000, queries=40)
-    ix = P.Index(w.n, w.m, w.h, capacity=20000, hash_seed=w.hash_seed)
+    stream = torch.cuda.Stream()  # a capturable (non-default) stream, default priority
+    torch.cuda.set_stream(stream)
+    ix = P.Index(w.n, w.m, w.h, capacity=20000, hash_seed=w.hash_seed, stream=stream)
     P.load_docs(ix, w.docs)
     t = _dev_batch(w.queries)
     dev = torch.device("cuda:0")
@@ -292,6 +294,8 @@ def test_graph_replays_match_eager_between_mutations():
         ix.delete_batch(np.arange(it * 50, it * 50 + 50))
         sub = extra.take(range(it * 80, it * 80 + 80))
         ix.insert_batch(np.arange(80) + 100000 + it * 100, sub.indptr, sub.coords, sub.vals)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream())
 
 
 def test_autotune_keeps_results_and_reports_schedule(small):
