@@ -557,8 +557,9 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
     return SNN_OK;
   }
   last_ws = p.w;
-  // graphs need a capturable stream: the legacy default stream is not one
-  if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr) {
+  // graphs need a capturable stream (the legacy default stream is not one);
+  // timed (profiled) passes launch eagerly so events can bracket the tile kernel
+  if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof_on && mode != SNN_MODE_PLAIN) {
       e0 = prof_event();
@@ -574,7 +575,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   // batched forms replay a captured HIP graph of the whole pass
   GraphKey key{};
   key.nq = nq; key.total = total; key.k = k; key.mode = mode; key.R = p.R; key.grid = p.grid;
-  key.persistent = p.persistent; key.tiles = p.tiles; key.prof = prof_on;
+  key.persistent = p.persistent; key.tiles = p.tiles; key.prof = false;
   key.ptr = d_ptr; key.c = d_c; key.v = d_v; key.ids = d_ids; key.sc = d_sc; key.cnt = d_cnt;
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
   key.ws = ws.p; key.cand = cand.p; key.cand2 = cand2.p;
@@ -582,10 +583,6 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   if (!g) {
     GraphEntry e;
     e.key = key;
-    if (prof_on) {
-      HIP_TRY(this, hipEventCreate(&e.ev0), "event");
-      HIP_TRY(this, hipEventCreate(&e.ev1), "event");
-    }
     hipGraph_t graph = nullptr;
     HIP_TRY(this, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
     snn_status est = enqueue_search(p, o, s, e.ev0, e.ev1);
@@ -605,14 +602,6 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
     g = graphs.insert(e);
   }
   HIP_TRY(this, hipGraphLaunch(g->exec, s), "graph launch");
-  if (prof_on && g->ev1) {
-    // the graph's event nodes are re-recorded by every replay: read them now
-    HIP_TRY(this, hipEventSynchronize(g->ev1), "event sync");
-    float ms = 0;
-    HIP_TRY(this, hipEventElapsedTime(&ms, g->ev0, g->ev1), "event time");
-    prof_accum_ms += ms;
-    prof_accum_n += 1;
-  }
   return SNN_OK;
 }
 
