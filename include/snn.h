@@ -165,6 +165,70 @@ snn_status snn_autotune(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint
 snn_status snn_get_schedule(snn_index *ix, snn_schedule *out);
 snn_status snn_set_schedule(snn_index *ix, const snn_schedule *in);
 
+/* ------------------------------------------------------------------------
+ * Learned k-th-score pre-filter (not part of the paper). A small MLP over
+ * hashed query features predicts y = ln(s_k), the log of the k-th Sinnamon
+ * score of the query. The search starts its selection threshold (theta of
+ * Alg. 3, otherwise minus infinity) at tau = exp(yhat - delta): only documents
+ * scoring >= tau are candidates. When at least min(k, live) documents reach
+ * tau, the k-th score is >= tau and the result is exactly the plain result;
+ * otherwise the query is re-run on the plain path. Results never change.
+ *
+ * Features (256): f[g(j)] += xi(j) q_j and f[128 + g(j)] += q_j^2 over nz(q),
+ * g(j) = mix64(mix64(feature_seed) ^ j) mod 128, xi(j) = -1 if the top bit of
+ * mix64(mix64(feature_seed + 1) ^ j) is set, else +1 (signed feature hashing).
+ * MLP: 256 -> 128 -> 128 -> 1 with ReLU, bf16 weights, fp32 accumulation; fp32
+ * master weights trained with Adam on mean squared error. Parameters are packed
+ * W1[128][256] | b1[128] | W2[128][128] | b2[128] | W3[128] | b3 (49,537
+ * floats, weights row-major [out][in]).
+ * ------------------------------------------------------------------------ */
+#define SNN_MLP_PARAMS 49537u
+#define SNN_MLP_FEATURES 256u
+
+typedef struct {
+  uint64_t feature_seed;
+  uint64_t seed;          /* weight initialisation and minibatch order */
+  uint32_t k;             /* the k whose k-th score is predicted */
+  uint32_t epochs;
+  uint32_t batch;         /* minibatch size */
+  float lr;               /* Adam learning rate */
+  float holdout;          /* fraction of labelled queries kept for calibration */
+  float target_fallback;  /* delta is the (1 - target) quantile of yhat - y on the holdout */
+} snn_filter_params;
+
+typedef struct {
+  uint32_t n_train, n_holdout, n_unlabelled;  /* unlabelled: s_k <= 0 or fewer than k results */
+  uint32_t steps;
+  float train_mse, holdout_mse;               /* on ln s_k */
+  float delta;
+  float holdout_fallback;                     /* fraction of holdout queries with s_k < tau */
+  float label_ms, train_ms;                   /* GPU time of labelling and of training */
+} snn_filter_report;
+
+/* Train the filter on nq device-resident training queries (CSR as in
+ * snn_search_batch_dev). Labels come from the plain search of this index.
+ * Blocking. Errors: SNN_E_INVALID (bad params, too few labelled queries). */
+snn_status snn_filter_train(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                            const uint32_t *coords, const float *vals, const snn_filter_params *params,
+                            snn_filter_report *report);
+/* Hashed features (device out: nq x 256 float32) and predictions yhat (device
+ * out: nq float32) of the current filter, enqueued on the index stream. */
+snn_status snn_filter_features(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                               const float *vals, float *out_features);
+snn_status snn_filter_predict(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                              const float *vals, float *out_yhat);
+/* Host copies of the parameters: get returns the bf16-rounded compute copies
+ * widened to float32; set loads float32 masters (the compute copies are their
+ * bf16 rounding) and resets the optimiser state. feature_seed and k come with
+ * set so a filter can be installed without training. */
+snn_status snn_filter_get_params(snn_index *ix, float *params);
+snn_status snn_filter_set_params(snn_index *ix, const float *params, uint64_t feature_seed, uint32_t k);
+snn_status snn_filter_set_delta(snn_index *ix, float delta);
+/* Loss and gradient of the MLP on B device-resident feature rows X (B x 256)
+ * and targets y, with the current compute copies: *loss (host) and grad
+ * (device, SNN_MLP_PARAMS floats). Used to check the training kernels. */
+snn_status snn_mlp_loss_grad(snn_index *ix, uint32_t B, const float *X, const float *y, float *grad, float *loss);
+
 /* Read back state for tests: the bucket table pi_o(j) as h x dim uint32
  * (row-major), and the stored sketch column (m floats each for U and L) of a
  * live id. Host pointers. */

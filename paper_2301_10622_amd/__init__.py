@@ -32,7 +32,10 @@ EXPORTS = [
     "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_autotune", "snn_get_schedule", "snn_set_schedule",
+    "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
+    "snn_filter_set_params", "snn_filter_set_delta", "snn_mlp_loss_grad",
 ]
+MLP_PARAMS = 49537
 
 
 class SnnError(RuntimeError):
@@ -45,6 +48,22 @@ class Schedule(ctypes.Structure):
     _fields_ = [("R_plain", ctypes.c_int32), ("R_batch", ctypes.c_int32), ("grid", ctypes.c_uint32),
                 ("persistent", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
                 ("tried", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class FilterParams(ctypes.Structure):
+    _fields_ = [("feature_seed", ctypes.c_uint64), ("seed", ctypes.c_uint64), ("k", ctypes.c_uint32),
+                ("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("holdout", ctypes.c_float), ("target_fallback", ctypes.c_float)]
+
+
+class FilterReport(ctypes.Structure):
+    _fields_ = [("n_train", ctypes.c_uint32), ("n_holdout", ctypes.c_uint32), ("n_unlabelled", ctypes.c_uint32),
+                ("steps", ctypes.c_uint32), ("train_mse", ctypes.c_float), ("holdout_mse", ctypes.c_float),
+                ("delta", ctypes.c_float), ("holdout_fallback", ctypes.c_float), ("label_ms", ctypes.c_float),
+                ("train_ms", ctypes.c_float)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -85,6 +104,13 @@ def lib():
         L.snn_autotune.argtypes = [P, u32, P, u64, P, P, u32, P]
         L.snn_get_schedule.argtypes = [P, P]
         L.snn_set_schedule.argtypes = [P, P]
+        L.snn_filter_train.argtypes = [P, u32, P, u64, P, P, P, P]
+        L.snn_filter_features.argtypes = [P, u32, P, P, P, P]
+        L.snn_filter_predict.argtypes = [P, u32, P, P, P, P]
+        L.snn_filter_get_params.argtypes = [P, P]
+        L.snn_filter_set_params.argtypes = [P, P, u64, u32]
+        L.snn_filter_set_delta.argtypes = [P, ctypes.c_float]
+        L.snn_mlp_loss_grad.argtypes = [P, u32, P, P, P, P]
         L.snn_live_count.argtypes = [P]
         L.snn_live_count.restype = sz
         L.snn_last_error.argtypes = [P]
@@ -92,7 +118,9 @@ def lib():
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
-                     "snn_get_schedule", "snn_set_schedule"):
+                     "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
+                     "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
+                     "snn_mlp_loss_grad"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -244,6 +272,52 @@ class Index:
     def set_schedule(self, R_plain=16, R_batch=32, grid=2048, persistent=True):
         sch = Schedule(R_plain, R_batch, grid, 1 if persistent else 0, 0.0, 0.0, 0)
         self._check(lib().snn_set_schedule(self._h, ctypes.byref(sch)))
+
+    # ------------------------------------------------------------- learned filter
+    def filter_train(self, indptr, coords, vals, k: int = 10, epochs: int = 8, batch: int = 512, lr: float = 1e-3,
+                     holdout: float = 0.1, target_fallback: float = 0.05, feature_seed: int = 12345, seed: int = 2,
+                     total: Optional[int] = None) -> dict:
+        """Train the k-th-score pre-filter on device-resident training queries."""
+        nq = indptr.numel() - 1
+        total = int(coords.numel()) if total is None else int(total)
+        p = FilterParams(feature_seed, seed, k, epochs, batch, lr, holdout, target_fallback)
+        rep = FilterReport()
+        self._check(lib().snn_filter_train(self._h, nq, _tp(indptr), total, _tp(coords), _tp(vals), ctypes.byref(p),
+                                           ctypes.byref(rep)))
+        return rep.as_dict()
+
+    def filter_features(self, indptr, coords, vals):
+        nq = indptr.numel() - 1
+        X = torch.empty((nq, 256), dtype=torch.float32, device=indptr.device)
+        self._check(lib().snn_filter_features(self._h, nq, _tp(indptr), _tp(coords), _tp(vals), _tp(X)))
+        return X
+
+    def filter_predict(self, indptr, coords, vals):
+        nq = indptr.numel() - 1
+        y = torch.empty(nq, dtype=torch.float32, device=indptr.device)
+        self._check(lib().snn_filter_predict(self._h, nq, _tp(indptr), _tp(coords), _tp(vals), _tp(y)))
+        return y
+
+    def filter_get_params(self) -> np.ndarray:
+        p = np.zeros(MLP_PARAMS, np.float32)
+        self._check(lib().snn_filter_get_params(self._h, _p(p)))
+        return p
+
+    def filter_set_params(self, params, feature_seed: int, k: int):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        self._check(lib().snn_filter_set_params(self._h, _p(p), feature_seed, k))
+
+    def filter_set_delta(self, delta: float):
+        self._check(lib().snn_filter_set_delta(self._h, float(delta)))
+
+    def mlp_loss_grad(self, X, y):
+        """(loss, grad) of the MLP on device feature rows X and targets y."""
+        B = X.shape[0]
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+        loss = ctypes.c_float()
+        self._check(lib().snn_mlp_loss_grad(self._h, B, _tp(X), _tp(y), _tp(g), ctypes.byref(loss)))
+        return float(loss.value), g
 
     # ------------------------------------------------------------- inspection
     def bucket_table(self) -> np.ndarray:

@@ -117,6 +117,8 @@ struct GraphCache {
 
 }  // namespace snn
 
+void snn_filter_release(struct snn_index *ix);
+
 struct snn_index {
   snn_config cfg{};
   uint32_t cap = 0, W = 0;

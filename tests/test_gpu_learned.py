@@ -1,0 +1,158 @@
+"""GPU checks of the learned k-th-score pre-filter: features and MLP gradients
+against the FP64 oracle, and search results identical to the plain method."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+
+FSEED = 12345
+
+
+def _dev(q):
+    import torch
+
+    d = torch.device("cuda:0")
+    return (torch.tensor(q.indptr, dtype=torch.int64, device=d), torch.tensor(q.coords.astype(np.int32), device=d),
+            torch.tensor(q.vals, device=d))
+
+
+def _unpack(p):
+    o = 0
+    out = {}
+    for k, shp in O.MLP_SHAPES.items():
+        n = int(np.prod(shp))
+        out[k] = np.asarray(p[o:o + n], dtype=np.float64).reshape(shp)
+        o += n
+    return out
+
+
+@pytest.fixture(scope="module")
+def small():
+    import paper_2301_10622_amd as P
+
+    w = gen.make_small(0)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
+    P.load_docs(ix, w.docs)
+    return w, ix
+
+
+def test_features_match_oracle(small):
+    w, ix = small
+    rng = np.random.default_rng(0)
+    ix.filter_set_params(rng.standard_normal(49537).astype(np.float32) * 0.05, FSEED, 10)
+    q = gen.small_queries(77, 64)
+    X = ix.filter_features(*_dev(q)).cpu().numpy()
+    for i in range(q.rows):
+        c, v = q.row(i)
+        f = O.features(c, v, FSEED)
+        np.testing.assert_allclose(X[i], f, rtol=1e-5, atol=1e-5)
+
+
+def test_mlp_forward_and_gradients_match_oracle(small):
+    """GPU loss and gradients (bf16 weights, fp32 accumulation) against FP64
+    back-propagation on the same bf16-rounded weights and fp32 inputs."""
+    import torch
+
+    w, ix = small
+    rng = np.random.default_rng(1)
+    p = np.concatenate([rng.standard_normal(32768) * np.sqrt(2 / 256), rng.standard_normal(128) * 0.1,
+                        rng.standard_normal(16384) * np.sqrt(2 / 128), rng.standard_normal(128) * 0.1,
+                        rng.standard_normal(128) * 0.1, [2.0]]).astype(np.float32)
+    ix.filter_set_params(p, FSEED, 10)
+    pb = _unpack(ix.filter_get_params())  # the bf16 compute copies the kernels use
+    q = gen.small_queries(78, 300)
+    Xd = ix.filter_features(*_dev(q))
+    X = Xd.cpu().numpy().astype(np.float64)
+    y = rng.normal(2.5, 0.4, q.rows)
+    yd = torch.tensor(y.astype(np.float32), device=Xd.device)
+    yh = ix.filter_predict(*_dev(q)).cpu().numpy()
+    np.testing.assert_allclose(yh, O.mlp_forward(X, pb), rtol=1e-4, atol=1e-4)
+    loss, g = ix.mlp_loss_grad(Xd, yd)
+    oloss, og = O.mlp_loss_grad(X, y.astype(np.float32).astype(np.float64), pb)
+    assert abs(loss - oloss) <= 1e-4 * max(1.0, oloss)
+    g = _unpack(g.cpu().numpy())
+    for name in O.MLP_SHAPES:
+        a, b = g[name].ravel(), og[name].ravel()
+        assert np.linalg.norm(a - b) <= 1e-3 * max(np.linalg.norm(b), 1e-6), name
+        big = np.abs(b) > 1e-3 * np.abs(b).max()
+        np.testing.assert_allclose(a[big], b[big], rtol=1e-2, atol=1e-6 * np.abs(b).max())
+
+
+@pytest.fixture(scope="module")
+def trained(small):
+    w, ix = small
+    tq = gen.small_queries(2, 20000)
+    rep = ix.filter_train(*_dev(tq), k=10, epochs=6, batch=512, lr=1e-3, feature_seed=FSEED)
+    return w, ix, rep
+
+
+def test_training_learns_the_kth_score(trained):
+    w, ix, rep = trained
+    assert rep["n_train"] > 15000 and rep["n_holdout"] > 1500 and rep["steps"] > 100
+    # a constant predictor has MSE = var(y); the network must do far better
+    tq = gen.small_queries(2, 20000)
+    ids, sc, cnt = ix.search_batch(tq.indptr[:2001], tq.coords[:tq.indptr[2000]], tq.vals[:tq.indptr[2000]], 10)
+    y = np.log(sc[:, 9][sc[:, 9] > 0].astype(np.float64))
+    assert rep["holdout_mse"] < 0.5 * np.var(y), (rep, np.var(y))
+    assert rep["holdout_fallback"] <= 0.06
+
+
+def _dev_search(ix, t, k, mode):
+    import torch
+
+    ids, sc, cnt = ix.search_batch_dev(*t, k, mode=mode)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), sc.cpu().numpy(), cnt.cpu().numpy()
+
+
+@pytest.mark.parametrize("k", [10, 5, 40])
+def test_learned_results_identical_to_plain(trained, k):
+    import paper_2301_10622_amd as P
+
+    w, ix, rep = trained
+    t = _dev(gen.small_queries(3, 2048))
+    plain = _dev_search(ix, t, k, P.MODE_BATCHED)
+    learned = _dev_search(ix, t, k, P.MODE_LEARNED)
+    inv, fb = ix.last_batch_status()
+    assert inv == 0
+    for a, b in zip(plain, learned):
+        assert np.array_equal(a, b)
+    if k == 10:
+        assert fb <= 0.15 * 2048, fb  # calibrated for about 5%
+
+
+def test_forced_fallback_and_pass_all(trained):
+    import paper_2301_10622_amd as P
+
+    w, ix, rep = trained
+    t = _dev(gen.small_queries(4, 300))
+    plain = _dev_search(ix, t, 10, P.MODE_BATCHED)
+    try:
+        for delta, expect_all in ((-np.inf, True), (np.inf, False), (-50.0, True)):
+            ix.filter_set_delta(delta)
+            got = _dev_search(ix, t, 10, P.MODE_LEARNED)
+            inv, fb = ix.last_batch_status()
+            for a, b in zip(plain, got):
+                assert np.array_equal(a, b), delta
+            assert (fb == 300) if expect_all else (fb == 0), (delta, fb)
+    finally:
+        ix.filter_set_delta(rep["delta"])
+
+
+def test_learned_after_mutations_stays_identical(trained):
+    """The filter is a pre-filter only: after deletes and inserts (no retraining)
+    results still equal the plain method."""
+    import paper_2301_10622_amd as P
+
+    w, ix, rep = trained
+    extra = gen.small_docs(55, 500)
+    ix.delete_batch(np.arange(0, 1000, 3))
+    ix.insert_batch(np.arange(500) + 50000, extra.indptr, extra.coords, extra.vals)
+    t = _dev(gen.small_queries(5, 512))
+    plain = _dev_search(ix, t, 10, P.MODE_BATCHED)
+    learned = _dev_search(ix, t, 10, P.MODE_LEARNED)
+    for a, b in zip(plain, learned):
+        assert np.array_equal(a, b)
