@@ -553,10 +553,12 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   snn_status st = plan_search(nq, d_ptr, total, d_c, d_v, k, mode, d_ids, d_sc, d_cnt, p);
   if (st != SNN_OK) return st;
   if (p.tiles == 0) {  // nothing was ever inserted: no results
+    last_status = nullptr;
     HIP_TRY(this, launch_fill_u32(d_cnt, 0u, nq, s), "fill");
     return SNN_OK;
   }
   last_ws = p.w;
+  last_status = p.w.status;
   // graphs need a capturable stream (the legacy default stream is not one);
   // timed (profiled) passes launch eagerly so events can bracket the tile kernel
   if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on) {
@@ -683,9 +685,10 @@ extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uin
 extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {
   if (!ix) return SNN_E_INVALID;
   uint32_t inv = 0;
-  if (ix->last_nq && ix->last_ws.status) {
+  if (ix->last_nq && ix->last_status) {
     std::vector<uint32_t> st(ix->last_nq);
-    HIP_TRY(ix, hipMemcpy(st.data(), ix->last_ws.status, (size_t)ix->last_nq * 4, hipMemcpyDeviceToHost), "status readback");
+    HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
+    HIP_TRY(ix, hipMemcpy(st.data(), ix->last_status, (size_t)ix->last_nq * 4, hipMemcpyDeviceToHost), "status readback");
     for (uint32_t v : st) inv += v != 0;
   }
   if (invalid_queries) *invalid_queries = inv;

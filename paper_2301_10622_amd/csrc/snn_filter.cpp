@@ -25,11 +25,11 @@ struct LearnedFilter {
   bool table_ok = false;
   uint32_t adam_t = 0;
   DevBuf P, Pb, M, V, G, table;
-  DevBuf X, yhat, thr, keff, sel, newptr, meta, fb_c, fb_v, fb_out;  // search scratch
+  DevBuf X, yhat, thr, keff, sel, newptr, meta, fb_c, fb_v, fb_out, stat;  // search scratch
   DevBuf tX, ty, trow, tyrow, H1, H2, D1, D2, DY, loss, tmpy;        // training scratch
   void release() {
     for (DevBuf *b : {&P, &Pb, &M, &V, &G, &table, &X, &yhat, &thr, &keff, &sel, &newptr, &meta, &fb_c, &fb_v,
-                      &fb_out, &tX, &ty, &trow, &tyrow, &H1, &H2, &D1, &D2, &DY, &loss, &tmpy})
+                      &fb_out, &stat, &tX, &ty, &trow, &tyrow, &H1, &H2, &D1, &D2, &DY, &loss, &tmpy})
       b->release();
   }
 };
@@ -373,10 +373,13 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
   o.keff = (const uint32_t *)f->keff.p;
   st = run_search(nq, d_ptr, total, d_c, d_v, k, SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, o);
   if (st != SNN_OK) return st;
-  if (!last_ws.fallback) {  // empty index: nothing to check
+  if (!last_status) {  // empty index: nothing to check
     last_fallbacks = 0;
     return SNN_OK;
   }
+  // keep this batch's per-query status: the fallback pass below reuses the workspace
+  HIP_TRY(this, f->stat.ensure((size_t)nq * 4, s), "status copy");
+  HIP_TRY(this, launch_copy_u32((uint32_t *)f->stat.p, last_status, nq, s), "status copy");
   // queries whose filter let fewer than min(k, live) documents through run again, plain
   HIP_TRY(this,
           launch_fallback_scan(nq, last_ws.fallback, d_ptr, (uint32_t *)f->sel.p, (uint64_t *)f->newptr.p,
@@ -386,6 +389,7 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
   HIP_TRY(this, hipMemcpyAsync(meta, f->meta.p, 16, hipMemcpyDeviceToHost, s), "fallback count");
   HIP_TRY(this, hipStreamSynchronize(s), "fallback sync");
   last_fallbacks = (uint32_t)meta[0];
+  last_status = (const uint32_t *)f->stat.p;
   if (meta[0] == 0) return SNN_OK;
   const uint32_t n = (uint32_t)meta[0];
   const uint64_t ne = meta[1];
@@ -404,6 +408,7 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
   if (st != SNN_OK) return st;
   HIP_TRY(this, launch_fallback_scatter(n, k, (uint32_t *)f->sel.p, fid, fsc, fcnt, d_ids, d_sc, d_cnt, s),
           "fallback scatter");
+  last_status = (const uint32_t *)f->stat.p;
   return SNN_OK;
 }
 

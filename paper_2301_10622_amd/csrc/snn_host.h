@@ -139,6 +139,7 @@ struct snn_index {
   snn::PinBuf pin;
   snn::SearchWs last_ws;
   uint32_t last_nq = 0, last_mode = 0, last_fallbacks = 0;
+  const uint32_t *last_status = nullptr;  // device: per-query status of the last batch
   snn::Tune tune;
   snn::LearnedFilter *filter = nullptr;
 
