@@ -44,7 +44,9 @@ def main():
     ap.add_argument("--docs", type=int, default=1_000_000)
     ap.add_argument("--queries", type=int, default=1024)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--forms", default="plain,batched")
+    ap.add_argument("--forms", default="plain,batched,learned")
+    ap.add_argument("--train-queries", type=int, default=50000)
+    ap.add_argument("--no-small", action="store_true", help="skip the learned-filter workload on the 10k-doc index")
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -140,12 +142,25 @@ def main():
 
     forms = {}
     outs = {}
+    filters = {}
     for name in args.forms.split(","):
         mode = {"plain": P.MODE_PLAIN, "batched": P.MODE_BATCHED, "learned": P.MODE_LEARNED}[name]
         for k in (args.k, 100):
             steps = args.plain_steps if name == "plain" else args.steps
             warm = 1 if name == "plain" else args.warmup
+            if name == "learned":
+                # the filter predicts the k-th score: train one for this k on
+                # separate training queries (labels from the plain method)
+                tq = gen.make_splade_like(2, docs=0, queries=args.train_queries).queries
+                tt = (torch.tensor(tq.indptr, dtype=torch.int64, device=dev),
+                      torch.tensor(tq.coords.astype(np.int32), device=dev), torch.tensor(tq.vals, device=dev))
+                rep = ix.filter_train(*tt, k=k, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz))
+                filters["k%d" % k] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rep.items()}
+                log("filter k=%d trained: %s" % (k, filters["k%d" % k]))
+                del tt
             r, out = run_form(mode, k, steps, warm)
+            if name == "learned":
+                r["fallbacks_last_step"] = ix.last_batch_status()[1]
             ab = alg_bytes(k)
             r["alg_bytes_per_step"] = ab
             r["alg_GBps"] = ab / (r["ms_per_step"] / 1000.0) / 1e9
@@ -178,6 +193,7 @@ def main():
         "forms": {n: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()} for n, r in forms.items()},
         "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1),
         "schedule": sched,
+        "filters": filters,
     }
 
     # ---------------------------------------------------------------- oracle
@@ -216,7 +232,51 @@ def main():
         log("oracle: %.2f q/s (estimate), %.2f q/s (exact); recall@%d %.4f" % (
             S / t_est, S / t_exact, args.k, result["recall_at_%d" % args.k]))
     ix.close()
+    if not args.no_small:
+        result["learned_small"] = small_learned(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def small_learned(args, dev, P, gen, np, torch):
+    """The learned-filter workload: the 10k-doc index, 200,000 training queries
+    labelled by the plain method, 8,192 evaluation queries, k = 10."""
+    w = gen.make_small(0)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=torch.cuda.current_stream())
+    P.load_docs(ix, w.docs)
+    tq = gen.small_queries(2, 200_000)
+    eq = gen.small_queries(3, 8192)
+    up = lambda q: (torch.tensor(q.indptr, dtype=torch.int64, device=dev),
+                    torch.tensor(q.coords.astype(np.int32), device=dev), torch.tensor(q.vals, device=dev))
+    tt, et = up(tq), up(eq)
+    sched = ix.autotune(*et, 10)
+    rep = ix.filter_train(*tt, k=10, epochs=8, batch=1024, lr=1e-3)
+    log("small: filter trained: %s" % rep)
+    nq = eq.rows
+    out = (torch.empty((nq, 10), dtype=torch.int32, device=dev), torch.empty((nq, 10), dtype=torch.float32, device=dev),
+           torch.empty(nq, dtype=torch.int32, device=dev))
+    res = {"workload": "small-10k-dim1000 learned filter, 8192 eval queries, k=10", "schedule": sched,
+           "filter": {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rep.items()}}
+    ref = None
+    for name, mode, steps in (("plain", P.MODE_PLAIN, 2), ("batched", P.MODE_BATCHED, 20), ("learned", P.MODE_LEARNED, 20)):
+        ix.search_batch_dev(*et, 10, mode=mode, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ix.search_batch_dev(*et, 10, mode=mode, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / steps
+        got = [x.cpu().numpy().copy() for x in out]
+        if ref is None:
+            ref = got
+        same = all(np.array_equal(a, b) for a, b in zip(ref, got))
+        res[name] = {"qps": round(nq / (ms / 1000), 1), "ms_per_step": round(ms, 4), "identical_to_plain": same}
+        if name == "learned":
+            res[name]["fallbacks"] = ix.last_batch_status()[1]
+        log("small %-8s %8.3f ms/step %10.0f q/s identical=%s" % (name, ms, nq / (ms / 1000), same))
+    res["learned_over_batched"] = round(res["learned"]["qps"] / res["batched"]["qps"], 3)
+    res["learned_over_plain"] = round(res["learned"]["qps"] / res["plain"]["qps"], 3)
+    ix.close()
+    return res
 
 
 if __name__ == "__main__":
