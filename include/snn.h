@@ -229,6 +229,56 @@ snn_status snn_filter_set_delta(snn_index *ix, float delta);
  * (device, SNN_MLP_PARAMS floats). Used to check the training kernels. */
 snn_status snn_mlp_loss_grad(snn_index *ix, uint32_t B, const float *X, const float *y, float *grad, float *loss);
 
+/* ------------------------------------------------------------------------
+ * Serving: one call runs a trace of searches, inserts and deletes against the
+ * device-resident index with continuous batching. Requests are admitted in
+ * arrival order. Inserts and deletes are applied as they arrive on the index
+ * stream; searches that arrive while earlier batches are on the GPU form the
+ * next batch, which is launched as soon as an in-flight slot and enough of the
+ * device memory budget are free, on its own stream, so batches overlap on the
+ * device. Every search sees exactly the inserts and deletes that precede it in
+ * the trace (the online setting of Section 1): slots changed during the run
+ * carry (insert, delete) sequence numbers, and a deleted slot is reused only
+ * once no search that may still see its old document is in flight.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint32_t n;                /* requests, in arrival order */
+  const uint8_t *kind;       /* 0 = search, 1 = insert, 2 = delete */
+  const double *arrival_s;   /* arrival time, seconds from the start, non-decreasing */
+  const uint32_t *id;        /* insert / delete: the document id */
+  const uint32_t *k;         /* search: k (1..4096) */
+  const uint64_t *indptr;    /* n + 1 offsets: the vector of request r (empty for deletes) */
+  const uint32_t *coords;
+  const float *vals;
+} snn_trace;
+
+typedef struct {
+  uint32_t max_batch;        /* most searches in one batch */
+  uint32_t max_inflight;     /* most batches on the device at once, 1..8 */
+  uint32_t streams;          /* HIP streams the batches rotate over, 1..4 */
+  uint32_t realtime;         /* 1: admit each request at its arrival time; 0: all arrive at once */
+  uint64_t budget_bytes;     /* device memory the in-flight search workspaces may use */
+} snn_serve_params;
+
+typedef struct {
+  uint32_t searches, inserts, deletes, rejected, batches, max_batch_seen, max_inflight_seen;
+  uint32_t reserved;
+  double wall_s, search_qps;
+  double p50_ms, p90_ms, p99_ms, max_ms, mean_ms; /* search latency: completion - arrival */
+  double mutation_p50_ms, mutation_p99_ms;        /* insert / delete latency */
+  uint64_t peak_workspace_bytes;
+} snn_serve_report;
+
+/* Run a trace (host pointers). The i-th search of the trace writes its results
+ * to row i of out_ids / out_scores (rows of kmax entries, kmax = the largest k
+ * in the trace), its count to out_counts[i] (0xFFFFFFFF when rejected because
+ * its own workspace exceeds the budget) and its latency to out_latency_ms[i]
+ * (any output pointer may be NULL). The trace is validated first
+ * (all-or-nothing): unknown kinds, inserts of live ids, deletes of ids that
+ * are not live at that point and malformed vectors give SNN_E_INVALID. */
+snn_status snn_serve_run(snn_index *ix, const snn_trace *trace, const snn_serve_params *params, uint32_t *out_ids,
+                         float *out_scores, uint32_t *out_counts, double *out_latency_ms, snn_serve_report *report);
+
 /* Read back state for tests: the bucket table pi_o(j) as h x dim uint32
  * (row-major), and the stored sketch column (m floats each for U and L) of a
  * live id. Host pointers. */

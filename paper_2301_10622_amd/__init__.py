@@ -33,7 +33,7 @@ EXPORTS = [
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
-    "snn_filter_set_params", "snn_filter_set_delta", "snn_mlp_loss_grad",
+    "snn_filter_set_params", "snn_filter_set_delta", "snn_mlp_loss_grad", "snn_serve_run",
 ]
 MLP_PARAMS = 49537
 
@@ -67,6 +67,30 @@ class FilterReport(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Trace(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("kind", ctypes.c_void_p), ("arrival_s", ctypes.c_void_p),
+                ("id", ctypes.c_void_p), ("k", ctypes.c_void_p), ("indptr", ctypes.c_void_p),
+                ("coords", ctypes.c_void_p), ("vals", ctypes.c_void_p)]
+
+
+class ServeParams(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("realtime", ctypes.c_uint32), ("budget_bytes", ctypes.c_uint64)]
+
+
+class ServeReport(ctypes.Structure):
+    _fields_ = [("searches", ctypes.c_uint32), ("inserts", ctypes.c_uint32), ("deletes", ctypes.c_uint32),
+                ("rejected", ctypes.c_uint32), ("batches", ctypes.c_uint32), ("max_batch_seen", ctypes.c_uint32),
+                ("max_inflight_seen", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("wall_s", ctypes.c_double),
+                ("search_qps", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p90_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("mutation_p50_ms", ctypes.c_double), ("mutation_p99_ms", ctypes.c_double),
+                ("peak_workspace_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class Config(ctypes.Structure):
@@ -111,6 +135,7 @@ def lib():
         L.snn_filter_set_params.argtypes = [P, P, u64, u32]
         L.snn_filter_set_delta.argtypes = [P, ctypes.c_float]
         L.snn_mlp_loss_grad.argtypes = [P, u32, P, P, P, P]
+        L.snn_serve_run.argtypes = [P, P, P, P, P, P, P, P]
         L.snn_live_count.argtypes = [P]
         L.snn_live_count.restype = sz
         L.snn_last_error.argtypes = [P]
@@ -120,7 +145,7 @@ def lib():
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
-                     "snn_mlp_loss_grad"):
+                     "snn_mlp_loss_grad", "snn_serve_run"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -318,6 +343,33 @@ class Index:
         loss = ctypes.c_float()
         self._check(lib().snn_mlp_loss_grad(self._h, B, _tp(X), _tp(y), _tp(g), ctypes.byref(loss)))
         return float(loss.value), g
+
+    # ------------------------------------------------------------- serving
+    def serve(self, kind, arrival_s, ids, k, indptr, coords, vals, max_batch=1024, max_inflight=3, streams=3,
+              realtime=True, budget_bytes=1 << 30):
+        """Run a request trace with continuous batching. Returns (ids, scores,
+        counts, latency_ms) per search, in trace order, and the report dict."""
+        kind = np.ascontiguousarray(kind, dtype=np.uint8)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        idv = np.ascontiguousarray(ids, dtype=np.uint32)
+        kv = np.ascontiguousarray(k, dtype=np.uint32)
+        ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        n = len(kind)
+        ns = int((kind == 0).sum())
+        kmax = int(kv[kind == 0].max()) if ns else 1
+        out_ids = np.zeros((ns, kmax), np.uint32)
+        out_sc = np.zeros((ns, kmax), np.float32)
+        out_cnt = np.zeros(ns, np.uint32)
+        lat = np.zeros(ns, np.float64)
+        tr = Trace(n, _p(kind).value, _p(arr).value, _p(idv).value, _p(kv).value, _p(ip).value, _p(c).value,
+                   _p(v).value)
+        pp = ServeParams(max_batch, max_inflight, streams, 1 if realtime else 0, budget_bytes)
+        rep = ServeReport()
+        self._check(lib().snn_serve_run(self._h, ctypes.byref(tr), ctypes.byref(pp), _p(out_ids), _p(out_sc),
+                                        _p(out_cnt), _p(lat), ctypes.byref(rep)))
+        return out_ids, out_sc, out_cnt, lat, rep.as_dict()
 
     # ------------------------------------------------------------- inspection
     def bucket_table(self) -> np.ndarray:

@@ -95,6 +95,45 @@ hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Serving snapshots. vis[slot] packs (insert seq << 32) | delete seq in one
+// 64-bit word, written and read whole, so a query never sees a torn pair; a
+// query with sequence t sees the slot iff insert seq < t < delete seq. Only
+// slots whose dirty bit is set are checked; every slot that is free when a
+// session starts is dirty from the start, deleted slots become dirty when the
+// delete is applied.
+// ---------------------------------------------------------------------------
+__global__ void k_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap) {
+  for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < cap; s += gridDim.x * blockDim.x) {
+    const bool lv = (live[slot_word(s)] >> slot_bit(s)) & 1ull;
+    vis[s] = lv ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull;  // live: always seen; free: never
+  }
+  for (uint32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < cap / 64; w += gridDim.x * blockDim.x)
+    dirty[w] = ~live[w];
+}
+
+hipError_t launch_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_serve_init, dim3(1024), dim3(256), 0, s, vis, dirty, live, cap);
+  return hipGetLastError();
+}
+
+__global__ void k_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const uint32_t *slots, const uint32_t *seqs,
+                             int is_insert) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t s = slots[i];
+  const uint64_t old = vis[s];
+  vis[s] = is_insert ? (((uint64_t)seqs[i] << 32) | 0xFFFFFFFFull) : ((old & 0xFFFFFFFF00000000ull) | seqs[i]);
+  atomicOr((unsigned long long *)&dirty[slot_word(s)], (unsigned long long)(1ull << slot_bit(s)));
+}
+
+hipError_t launch_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const uint32_t *slots, const uint32_t *seqs,
+                             int is_insert, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_serve_mark, dim3((n + 255) / 256), dim3(256), 0, s, vis, dirty, n, slots, seqs, is_insert);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     p[i] = v;
@@ -223,9 +262,10 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     const uint32_t lo = (uint32_t)k;
     const uint32_t j = lo >> 1;
     const uint32_t vb = ab | ((lo & 1u) << 31);
-    qd.j[e0 + i] = j;
-    qd.q[e0 + i] = __builtin_bit_cast(float, vb);
-    for (uint32_t o = 0; o < ix.h; ++o) qd.b[(e0 + i) * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+    const uint64_t e = e0 - qd.ebase + i;
+    qd.j[e] = j;
+    qd.q[e] = __builtin_bit_cast(float, vb);
+    for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
   }
   if (threadIdx.x == 0) {
     qd.cnt[q] = cnt;

@@ -135,7 +135,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
 #pragma unroll
   for (int x = 0; x < R; ++x) acc[x] = 0.0f;
 
-  const uint64_t e0 = as_const(a.qd.qptr)[q];
+  const uint64_t e0 = as_const(a.qd.qptr)[q] - a.qd.ebase;
   const uint32_t ne = as_const(a.qd.cnt)[q];
   const uint32_t h = ix.h;
   const cptr<uint32_t> qj = as_const(a.qd.j);
@@ -211,6 +211,21 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const float s = acc[x] == 0.0f ? 0.0f : acc[x];  // -0 -> +0
     const uint32_t kk = ord_key(s);
     key[x] = (lv && kk >= thr) ? kk : 0u;
+  }
+  if (a.qseq) {
+    // serving snapshot: a slot changed during the session is seen only if it was
+    // inserted before the query and not deleted before it
+    const uint32_t tq = as_const(a.qseq)[q];
+    const cptr<uint64_t> dw = as_const(a.dirty) + wword0;
+#pragma unroll
+    for (int x = 0; x < R; ++x) {
+      if (key[x] != 0u && __builtin_amdgcn_inverse_ballot_w64(dw[x])) {
+        const uint64_t v = __hip_atomic_load(const_cast<uint64_t *>(&a.vis[slot_of<R>(wslot0, x, lane)]),
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ins = (uint32_t)(v >> 32), del = (uint32_t)v;
+        if (!(ins < tq && tq < del)) key[x] = 0u;
+      }
+    }
   }
   int par = 0;
   uint32_t nvalid;

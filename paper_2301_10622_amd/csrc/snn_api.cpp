@@ -105,7 +105,7 @@ snn_status snn_index::hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 // Validate one sparse vector; appends its non-zero entries to out_c/out_v.
-static bool check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v, std::vector<uint32_t> &oc,
+bool snn_check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v, std::vector<uint32_t> &oc,
                          std::vector<float> &ov, std::vector<uint32_t> &scratch, const char *what) {
   if (nnz && (!c || !v)) {
     ix->fail(SNN_E_INVALID, "%s: null coordinate or value pointer", what);
@@ -211,9 +211,7 @@ extern "C" void snn_destroy(snn_index *ix) {
   if (d.bucket) (void)hipFree(d.bucket);
   ix->up.release();
   ix->pin.release();
-  ix->ws.release();
-  ix->cand.release();
-  ix->cand2.release();
+  ix->wsp.release();
   delete ix;
 }
 
@@ -271,7 +269,7 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
     if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "insert: indptr not monotone");
     uint64_t len = indptr[r + 1] - indptr[r];
     if (len > ix->cfg.dim) return ix->fail(SNN_E_INVALID, "insert: vector with more entries than dim");
-    if (!check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "insert"))
+    if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "insert"))
       return SNN_E_INVALID;
     optr[r + 1] = oc.size();
   }
@@ -376,7 +374,8 @@ extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete
 
 // Device workspace for one batch: prepared entries, per-query state, tile
 // candidates. Laid out in one allocation.
-snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, SearchWs &w) {
+snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, SearchWs &w,
+                                        Workspace &W, hipStream_t stream) {
   const uint32_t h = cfg.h;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t o = 0;
@@ -391,12 +390,12 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
   const size_t o_cc2 = o; o += al((size_t)nq * tiles * 4);
   const size_t o_queue = o; o += al(64 * 4);
-  HIP_TRY(this, ws.ensure(o, stream), "search workspace");
+  HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
   const uint32_t F = merge_fanin(k);
   const uint32_t g1 = (tiles + F - 1) / F;
-  HIP_TRY(this, cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
-  HIP_TRY(this, cand2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 8 + 64, stream), "candidate buffer");
-  char *p = (char *)ws.p;
+  HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
+  HIP_TRY(this, W.cand2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 8 + 64, stream), "candidate buffer");
+  char *p = (char *)W.ws.p;
   w.cnt = (uint32_t *)(p + o_cnt);
   w.status = (uint32_t *)(p + o_status);
   w.thr = (uint32_t *)(p + o_thr);
@@ -408,8 +407,8 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.cand_cnt = (uint32_t *)(p + o_cc);
   w.cand_cnt2 = (uint32_t *)(p + o_cc2);
   w.queue = (uint32_t *)(p + o_queue);
-  w.cand = (uint64_t *)cand.p;
-  w.cand2 = (uint64_t *)cand2.p;
+  w.cand = (uint64_t *)W.cand.p;
+  w.cand2 = (uint64_t *)W.cand2.p;
   return SNN_OK;
 }
 
@@ -473,7 +472,7 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32
 snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t ev0,
                                      hipEvent_t ev1) {
   const SearchWs &w = p.w;
-  QueryDesc qd{p.d_ptr, w.cnt, w.status, w.j, w.q, w.b};
+  QueryDesc qd{p.d_ptr, w.cnt, w.status, w.j, w.q, w.b, o.ebase};
   HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, s), "prep kernel");
   if (o.thr_init) {
     HIP_TRY(this, launch_copy_u32(w.thr, o.thr_init, p.nq, s), "thr init");
@@ -492,6 +491,9 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   a.cand_cnt = w.cand_cnt;
   a.queue = w.queue;
   a.xcds = 8;
+  a.qseq = o.qseq;
+  a.vis = vis;
+  a.dirty = dirty;
   if (p.mode == SNN_MODE_PLAIN) {
     for (uint32_t q = 0; q < p.nq; ++q) {
       a.q0 = q;
@@ -526,7 +528,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
 
 snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
                                   const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
-                                  uint32_t *d_cnt, SearchPlan &p) {
+                                  uint32_t *d_cnt, SearchPlan &p, const SearchOpts &o, hipStream_t s) {
   p.nq = nq;
   p.d_ptr = d_ptr;
   p.total = total;
@@ -543,14 +545,14 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   const uint32_t tile_docs = (uint32_t)kBlock * p.R;
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
-  return prepare_workspace(nq, total, k, p.tiles, p.w);
+  return prepare_workspace(nq, total - o.ebase, k, p.tiles, p.w, o.wsp ? *o.wsp : wsp, s);
 }
 
 snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
                                  const float *d_v, uint32_t k, int mode, uint32_t *d_ids, float *d_sc,
                                  uint32_t *d_cnt, hipStream_t s, const SearchOpts &o) {
   SearchPlan p;
-  snn_status st = plan_search(nq, d_ptr, total, d_c, d_v, k, mode, d_ids, d_sc, d_cnt, p);
+  snn_status st = plan_search(nq, d_ptr, total, d_c, d_v, k, mode, d_ids, d_sc, d_cnt, p, o, s);
   if (st != SNN_OK) return st;
   if (p.tiles == 0) {  // nothing was ever inserted: no results
     last_status = nullptr;
@@ -561,7 +563,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   last_status = p.w.status;
   // graphs need a capturable stream (the legacy default stream is not one);
   // timed (profiled) passes launch eagerly so events can bracket the tile kernel
-  if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on) {
+  if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on || o.no_graph) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof_on && mode != SNN_MODE_PLAIN) {
       e0 = prof_event();
@@ -580,7 +582,8 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.persistent = p.persistent; key.tiles = p.tiles; key.prof = false;
   key.ptr = d_ptr; key.c = d_c; key.v = d_v; key.ids = d_ids; key.sc = d_sc; key.cnt = d_cnt;
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
-  key.ws = ws.p; key.cand = cand.p; key.cand2 = cand2.p;
+  Workspace &W = o.wsp ? *o.wsp : wsp;
+  key.ws = W.ws.p; key.cand = W.cand.p; key.cand2 = W.cand2.p; key.qseq = o.qseq; key.ebase = o.ebase;
   GraphEntry *g = graphs.find(key);
   if (!g) {
     GraphEntry e;
@@ -622,7 +625,7 @@ extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_
     if (len > (uint64_t)kPrepCap) return ix->fail(SNN_E_INVALID, "search: a query has more than %d entries", kPrepCap);
     oc.clear();
     ov.clear();
-    if (!check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "search"))
+    if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "search"))
       return SNN_E_INVALID;
   }
   const uint64_t total = indptr[nq];

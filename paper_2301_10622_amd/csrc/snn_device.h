@@ -42,12 +42,13 @@ struct DevIndex {
 // Prepared queries (Alg. 6 first steps): entry e of query q sits at qptr[q] + i
 // for i < cnt[q], sorted by |q_j| descending, ties by lower j.
 struct QueryDesc {
-  const uint64_t *qptr;  // [nq + 1] (the caller's CSR offsets)
+  const uint64_t *qptr;  // [nq + 1] (the caller's CSR offsets; entry e sits at e - ebase below)
   uint32_t *cnt;         // [nq] non-zero entries after preparation
   uint32_t *status;      // [nq] 0 = ok, else malformed
   uint32_t *j;           // [total]
   float *q;              // [total]
   uint32_t *b;           // [total * h]
+  uint64_t ebase;        // qptr value of the first entry held in j, q, b
 };
 
 struct TileArgs {
@@ -64,6 +65,10 @@ struct TileArgs {
   // persistent schedule
   uint32_t *queue;    // [8] per-XCD work counters (zeroed before launch)
   uint32_t xcds;      // number of per-XCD queues
+  // snapshot visibility while serving (qseq null: every live slot is visible)
+  const uint32_t *qseq;   // [nq] sequence number of each query
+  const uint64_t *vis;    // [cap] (insert seq << 32) | delete seq
+  const uint64_t *dirty;  // bitmap, slot layout of `live`: slot changed during the session
 };
 
 struct MergeArgs {
@@ -102,6 +107,9 @@ __host__ __device__ inline float key_value(uint32_t k) {
 // launchers (return hipError_t of the launch)
 hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
                          const uint64_t *indptr, const uint32_t *coords, const float *vals, hipStream_t s);
+hipError_t launch_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const uint32_t *slots,
+                             const uint32_t *seqs, int is_insert, hipStream_t s);
+hipError_t launch_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap, hipStream_t s);
 hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,
                          const uint32_t *coords, int clear_bits, int clear_live, hipStream_t s);
 hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,

@@ -28,6 +28,16 @@ struct PinBuf {
   void release();
 };
 
+// Device buffers of one in-flight search batch.
+struct Workspace {
+  DevBuf ws, cand, cand2;
+  void release() {
+    ws.release();
+    cand.release();
+    cand2.release();
+  }
+};
+
 struct SearchWs {
   uint32_t *cnt = nullptr, *status = nullptr, *thr = nullptr, *fallback = nullptr, *keff = nullptr;
   uint32_t *j = nullptr, *b = nullptr;
@@ -51,6 +61,10 @@ struct SearchOpts {
   const uint32_t *thr_init = nullptr;  // initial inclusive threshold keys (learned filter)
   const uint32_t *kq = nullptr;        // per-query k (<= the batch k)
   const uint32_t *keff = nullptr;      // count below which the filter check reports a fallback
+  const uint32_t *qseq = nullptr;      // serving: per-query sequence numbers (snapshot visibility)
+  uint64_t ebase = 0;                  // indptr value of the batch's first entry
+  Workspace *wsp = nullptr;            // buffers (null: the index's own)
+  bool no_graph = false;
 };
 
 struct SearchPlan {
@@ -70,13 +84,15 @@ struct GraphKey {
   uint32_t nq, k, mode, R, grid, tiles;
   uint64_t total;
   bool persistent, prof;
-  const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2;
+  const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2, *qseq;
+  uint64_t ebase;
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
-           ws == o.ws && cand == o.cand && cand2 == o.cand2 && stream == o.stream;
+           ws == o.ws && cand == o.cand && cand2 == o.cand2 && qseq == o.qseq && ebase == o.ebase &&
+           stream == o.stream;
   }
 };
 
@@ -118,6 +134,9 @@ struct GraphCache {
 }  // namespace snn
 
 void snn_filter_release(struct snn_index *ix);
+bool snn_check_vector(struct snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v,
+                      std::vector<uint32_t> &oc, std::vector<float> &ov, std::vector<uint32_t> &scratch,
+                      const char *what);
 
 struct snn_index {
   snn_config cfg{};
@@ -135,7 +154,9 @@ struct snn_index {
   uint64_t mutations = 0;
 
   // buffers
-  snn::DevBuf up, ws, cand, cand2;
+  snn::DevBuf up;
+  snn::Workspace wsp;
+  uint64_t *vis = nullptr, *dirty = nullptr;  // serving snapshot state (allocated by snn_serve_run)
   snn::PinBuf pin;
   snn::SearchWs last_ws;
   uint32_t last_nq = 0, last_mode = 0, last_fallbacks = 0;
@@ -167,13 +188,15 @@ struct snn_index {
                                const std::vector<float> &vals, size_t r0, size_t r1);
   snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
-  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, snn::SearchWs &w);
+  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, snn::SearchWs &w,
+                               snn::Workspace &W, hipStream_t s);
   uint32_t merge_fanin(uint32_t k) const;
   snn_status enqueue_merge(const snn::SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
                            uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids, float *res_scores,
                            uint32_t *res_cnt, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
-                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p);
+                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p,
+                         const snn::SearchOpts &o, hipStream_t s);
   snn_status enqueue_search(const snn::SearchPlan &p, const snn::SearchOpts &o, hipStream_t s, hipEvent_t ev0,
                             hipEvent_t ev1);
   snn_status run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,

@@ -318,3 +318,26 @@ def serving_trace(seed: int, ops: int, live_ids: np.ndarray, next_id: int, rate_
     queries = serving_queries(seed + 1, nq)
     docs = small_docs(seed + 2, ni)
     return dict(kind=kind, t=t, ids=ids, k=kk, queries=queries, docs=docs)
+
+
+def trace_csr(tr: dict) -> CSR:
+    """Per-request vectors of a serving trace in request order (queries and
+    inserted documents; deletes get an empty row)."""
+    kind = tr["kind"]
+    q, d = tr["queries"], tr["docs"]
+    lens = np.zeros(len(kind), dtype=np.int64)
+    qi = np.nonzero(kind == 0)[0]
+    di = np.nonzero(kind == 1)[0]
+    lens[qi] = np.diff(q.indptr)
+    lens[di] = np.diff(d.indptr)
+    indptr = np.zeros(len(kind) + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    coords = np.zeros(int(indptr[-1]), dtype=np.uint32)
+    vals = np.zeros(int(indptr[-1]), dtype=np.float32)
+    for rows, src in ((qi, q), (di, d)):
+        for j, r in enumerate(rows):
+            a, b = int(indptr[r]), int(indptr[r + 1])
+            c, v = src.row(j)
+            coords[a:b] = c
+            vals[a:b] = v
+    return CSR(indptr, coords, vals)

@@ -1,0 +1,142 @@
+"""Serving: each search result in the interleaved, continuously batched run is
+the result of that search alone against the index state at its position in the
+trace (the live set after exactly the preceding inserts and deletes)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import gen
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(seed=0, prefill=12000, capacity=20000):
+    import paper_2301_10622_amd as P
+
+    docs = gen.small_docs(seed, prefill)
+    ix = P.Index(1000, 32, 1, capacity=capacity, hash_seed=seed)
+    P.load_docs(ix, docs)
+    return ix, docs
+
+
+def _trace(seed, ops, live_ids, next_id, rate):
+    tr = gen.serving_trace(seed, ops, live_ids, next_id, rate, ks=(10, 100, 1000))
+    csr = gen.trace_csr(tr)
+    return tr, csr
+
+
+def _live_states(docs, tr, csr, sample):
+    """Live {id: (coords, vals)} just before each sampled request index."""
+    live = {i: docs.row(i) for i in range(docs.rows)}
+    out = {}
+    want = set(sample)
+    for r in range(len(tr["kind"])):
+        if r in want:
+            out[r] = dict(live)
+        kd = tr["kind"][r]
+        if kd == 1:
+            live[int(tr["ids"][r])] = csr.row(r)
+        elif kd == 2:
+            del live[int(tr["ids"][r])]
+    return out
+
+
+def _oracle_for(state):
+    ids = np.array(sorted(state), dtype=np.uint32)
+    rows = [state[int(i)] for i in ids]
+    lens = np.array([len(c) for c, _ in rows], dtype=np.int64)
+    indptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    csr = gen.CSR(indptr, np.concatenate([c for c, _ in rows]).astype(np.uint32),
+                  np.concatenate([v for _, v in rows]).astype(np.float32))
+    return O.Index(csr, 1000, 32, 1, 0, ids=ids), csr, ids
+
+
+def test_serving_results_equal_alone_at_their_snapshot():
+    import paper_2301_10622_amd as P
+
+    ix, docs = _setup()
+    tr, csr = _trace(0, 3000, np.arange(docs.rows), docs.rows, rate=20000.0)
+    res_ids, res_sc, res_cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords,
+                                                  csr.vals, max_batch=256, max_inflight=3, streams=3, realtime=True,
+                                                  budget_bytes=1 << 30)
+    kind = tr["kind"]
+    sreq = np.nonzero(kind == 0)[0]
+    assert rep["searches"] == len(sreq) and rep["rejected"] == 0
+    assert rep["inserts"] == int((kind == 1).sum()) and rep["deletes"] == int((kind == 2).sum())
+    assert rep["p99_ms"] >= rep["p50_ms"] > 0 and np.all(lat > 0)
+    # the index after the run holds exactly the final live set
+    final = _live_states(docs, tr, csr, [len(kind) - 1])[len(kind) - 1]
+    last = len(kind) - 1
+    if kind[last] == 1:
+        final[int(tr["ids"][last])] = csr.row(last)
+    elif kind[last] == 2:
+        del final[int(tr["ids"][last])]
+    assert ix.live_count == len(final)
+    # sampled searches against the FP64 oracle on their own snapshot
+    rng = np.random.default_rng(0)
+    pick = sorted(rng.choice(len(sreq), 40, replace=False).tolist())
+    states = _live_states(docs, tr, csr, [int(sreq[i]) for i in pick])
+    for i in pick:
+        r = int(sreq[i])
+        ora, _, ids = _oracle_for(states[r])
+        qc, qv = csr.row(r)
+        s, a = ora.score_all(qc, qv)
+        k = int(tr["k"][r])
+        pos_of_id = {int(x): p for p, x in enumerate(ids)}
+        c = int(res_cnt[i])
+        parity.check_query(res_ids[i][:c], res_sc[i][:c], s, a, pos_of_id, ids.astype(np.int64), k,
+                           what="serve search %d (request %d)" % (i, r))
+    # and a few bit-exactly against the same search alone on a fresh GPU index of that snapshot
+    for i in pick[:6]:
+        r = int(sreq[i])
+        _, snap, ids = _oracle_for(states[r])
+        alone = P.Index(1000, 32, 1, capacity=max(len(ids), 1), hash_seed=0)
+        P.load_docs(alone, snap, ids=ids)
+        qc, qv = csr.row(r)
+        a_ids, a_sc = alone.search(qc, qv, int(tr["k"][r]))
+        c = int(res_cnt[i])
+        assert np.array_equal(a_ids, res_ids[i][:c]) and np.array_equal(a_sc, res_sc[i][:c]), i
+        alone.close()
+
+
+def test_serving_overlaps_batches_and_admits_by_budget():
+    ix, docs = _setup(1, prefill=8000, capacity=12000)
+    tr, csr = _trace(1, 1500, np.arange(docs.rows), docs.rows, rate=1e9)
+    # all requests arrive at once: batches queue behind each other and overlap on the device
+    _, _, cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords, csr.vals,
+                                   max_batch=64, max_inflight=4, streams=4, realtime=False, budget_bytes=1 << 30)
+    assert rep["batches"] >= 10 and rep["max_inflight_seen"] >= 2 and rep["rejected"] == 0
+    # a budget below one k = 1000 search's workspace (on this small index about 32 KB,
+    # k = 100 about 4 KB): those are rejected, the rest run within the budget
+    ix2, docs2 = _setup(1, prefill=8000, capacity=12000)
+    budget = 20 << 10
+    _, _, cnt2, lat2, rep2 = ix2.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords, csr.vals,
+                                       max_batch=64, max_inflight=2, streams=2, realtime=False, budget_bytes=budget)
+    k1000 = tr["k"][tr["kind"] == 0] == 1000
+    assert rep2["rejected"] == int(k1000.sum()) > 0
+    assert np.all(cnt2[k1000] == 0xFFFFFFFF) and np.all(cnt2[~k1000] > 0)
+    assert 0 < rep2["peak_workspace_bytes"] <= budget
+
+
+def test_serving_rejects_malformed_traces_without_changes():
+    import paper_2301_10622_amd as P
+
+    ix, docs = _setup(2, prefill=1000, capacity=2000)
+    before = ix.live_count
+    e = np.zeros(0)
+    bad = [
+        # delete of an id that is not live
+        (np.array([2], np.uint8), np.array([0.0]), np.array([99999]), np.array([0]), np.array([0, 0])),
+        # insert of a live id
+        (np.array([1], np.uint8), np.array([0.0]), np.array([5]), np.array([0]), np.array([0, 1])),
+        # unknown kind
+        (np.array([7], np.uint8), np.array([0.0]), np.array([0]), np.array([0]), np.array([0, 0])),
+    ]
+    for kind, t, ids, k, ip in bad:
+        with pytest.raises(P.SnnError) as ex:
+            ix.serve(kind, t, ids, k, ip, np.array([3] * int(ip[-1]), np.uint32),
+                     np.ones(int(ip[-1]), np.float32))
+        assert ex.value.status == -1
+    assert ix.live_count == before
