@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--forms", default="plain,batched,learned")
     ap.add_argument("--train-queries", type=int, default=50000)
     ap.add_argument("--no-small", action="store_true", help="skip the learned-filter workload on the 10k-doc index")
+    ap.add_argument("--no-batch4m", action="store_true", help="skip the 4M-doc batching workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the 8M-capacity serving workload")
+    ap.add_argument("--serving-ops", type=int, default=100_000)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -234,7 +237,92 @@ def main():
     ix.close()
     if not args.no_small:
         result["learned_small"] = small_learned(args, dev, P, gen, np, torch)
+    if not args.no_batch4m:
+        result["batch_4m"] = batch_4m(args, dev, P, gen, np, torch)
+    if not args.no_serving:
+        result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def _rounded(d):
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def batch_4m(args, dev, P, gen, np, torch):
+    """Batching workload: 4M docs with the small-index laws, 8,192 queries of nnz
+    log-uniform 5..400 in one persistent launch per batch, k = 100."""
+    t = time.time()
+    w = gen.make_batch(0)
+    log("batch4m: generated %d docs / %d queries in %.1fs" % (w.docs.rows, w.queries.rows, time.time() - t))
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=torch.cuda.current_stream())
+    P.load_docs(ix, w.docs)
+    up = lambda q: (torch.tensor(q.indptr, dtype=torch.int64, device=dev),
+                    torch.tensor(q.coords.astype(np.int32), device=dev), torch.tensor(q.vals, device=dev))
+    et = up(w.queries)
+    nq, k = w.queries.rows, 100
+    list_len = np.bincount(w.docs.coords, minlength=w.n).astype(np.int64)
+    post = np.add.reduceat(list_len[w.queries.coords], w.queries.indptr[:-1])
+    ab = float((post * 8 + 12 * np.diff(w.queries.indptr) + 8 * k).sum())
+    sched = ix.autotune(*et, k)
+    res = {"workload": w.name, "docs": w.docs.rows, "queries_per_step": nq, "k": k, "schedule": sched,
+           "alg_bytes_per_step": ab}
+    out = (torch.empty((nq, k), dtype=torch.int32, device=dev), torch.empty((nq, k), dtype=torch.float32, device=dev),
+           torch.empty(nq, dtype=torch.int32, device=dev))
+    for name, mode, steps in (("plain", P.MODE_PLAIN, 1), ("batched", P.MODE_BATCHED, 5)):
+        ix.search_batch_dev(*et, k, mode=mode, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ix.search_batch_dev(*et, k, mode=mode, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000 / steps
+        res[name] = {"qps": round(nq / (ms / 1000), 1), "ms_per_step": round(ms, 3),
+                     "alg_GBps": round(ab / (ms / 1000) / 1e9, 1)}
+        log("batch4m %-8s %9.3f ms/step %10.0f q/s alg %.0f GB/s" % (name, ms, nq / (ms / 1000), ab / (ms / 1000) / 1e9))
+    res["batched_over_plain"] = round(res["batched"]["qps"] / res["plain"]["qps"], 2)
+    ix.close()
+    return res
+
+
+def serving_8m(args, dev, P, gen, np, torch):
+    """Serving workload: capacity 8M slots, 4M prefilled small-law docs; Poisson
+    arrivals of 85% searches (nnz lognormal mean 40, k in {10, 100, 1000}), 10%
+    inserts, 5% deletes; admission by a device-memory budget; p50 / p99."""
+    t = time.time()
+    docs = gen.small_docs(0, 4_000_000)
+    log("serving: generated prefill in %.1fs" % (time.time() - t))
+    ix = P.Index(1000, 32, 1, capacity=8_000_000, hash_seed=0, stream=torch.cuda.current_stream())
+    P.load_docs(ix, docs)
+    ops = args.serving_ops
+    res = {"workload": "serving capacity 8M, 4M prefill, %d ops, 85/10/5 search/insert/delete" % ops}
+    budget = 8 << 30
+
+    live = {"ids": np.arange(docs.rows, dtype=np.int64)}
+
+    def run(rate, realtime, seed):
+        tr = gen.serving_trace(seed, ops, live["ids"], 10_000_000 + seed * 1_000_000, rate)
+        csr = gen.trace_csr(tr)
+        # the live set after this trace (the next trace deletes from it)
+        gone = set(tr["ids"][tr["kind"] == 2].tolist())
+        keep = live["ids"][~np.isin(live["ids"], list(gone))] if gone else live["ids"]
+        live["ids"] = np.concatenate([keep, tr["ids"][tr["kind"] == 1].astype(np.int64)])
+        _, _, cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords, csr.vals,
+                                       max_batch=1024, max_inflight=3, streams=3, realtime=realtime,
+                                       budget_bytes=budget)
+        return _rounded(rep)
+
+    sat = run(1e9, False, 1)
+    res["saturated"] = sat
+    log("serving saturated: %.0f q/s (batches %d, max in flight %d)" % (
+        sat["search_qps"], sat["batches"], sat["max_inflight_seen"]))
+    for frac, seed in ((0.5, 2), (0.8, 3), (0.95, 4)):
+        rep = run(sat["search_qps"] * frac, True, seed)
+        res["load_%.2f" % frac] = rep
+        log("serving at %.2f x saturation: %.0f q/s  p50 %.3f ms  p99 %.3f ms  mutations p99 %.3f ms" % (
+            frac, rep["search_qps"], rep["p50_ms"], rep["p99_ms"], rep["mutation_p99_ms"]))
+    res["budget_bytes"] = budget
+    ix.close()
+    return res
 
 
 def small_learned(args, dev, P, gen, np, torch):
