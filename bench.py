@@ -181,10 +181,15 @@ def main():
     per_launch_queries = nq / head["tile_launches_per_step"]
     ab_launch = alg_bytes(args.k) * per_launch_queries / nq
     achieved = ab_launch / (launch_ms / 1000.0) / 1e9
+    kname = ("k_tiles_persistent<%d>" if best != "plain" else "k_tiles<%d>") % (
+        sched["R_batch"] if best != "plain" else sched["R_plain"])
+    traffic = measured_traffic(kname, args.k)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_tiles_persistent" if best != "plain" else "k_tiles",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
                 "alg_bytes_per_launch": ab_launch, "launch_ms": launch_ms}
+    if traffic:
+        roofline["traffic_GBps"] = round(traffic / (launch_ms / 1000.0) / 1e9, 1)
+        roofline["traffic_over_alg_bytes"] = round(traffic / ab_launch, 4)
 
     result = {
         "metric": METRIC, "value": round(head["qps"], 1), "unit": "queries/s", "n_gpus": 1,
@@ -242,6 +247,28 @@ def main():
     if not args.no_serving:
         result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def measured_traffic(kernel, k):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    passes (calibrated against a plain copy), or None when the kernel source has
+    changed since they were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for f in ("paper_2301_10622_amd/csrc/kernels_search.hip", "paper_2301_10622_amd/csrc/snn_device.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    if k == 100 and "k100" in rec:
+        return rec["k100"]["traffic_bytes_per_launch"]
+    return rec["traffic_bytes_per_launch"] if k == 10 else None
 
 
 def _rounded(d):
