@@ -208,6 +208,46 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     return;
   }
   const int len = (int)len64;
+  if (len <= 256) {
+    // short queries: rank counting instead of sorting (one barrier). Keys of
+    // distinct coordinates are distinct; equal coordinates are duplicates.
+    __shared__ uint32_t sj[256];
+    const int t = threadIdx.x;
+    uint64_t key = ~0ull;
+    uint32_t j = 0xFFFFFFFFu;
+    if (t < len) {
+      j = coords[e0 + t];
+      const uint32_t vb = __builtin_bit_cast(uint32_t, vals[e0 + t]);
+      const uint32_t ab = vb & 0x7FFFFFFFu;
+      if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
+      if (ab != 0u) {
+        atomicAdd(&nz, 1u);
+        key = ((uint64_t)(~ab) << 32) | ((uint64_t)(j & 0x7FFFFFFFu) << 1) | (uint64_t)(vb >> 31);
+      }
+      keys[t] = key;
+      sj[t] = j;
+    }
+    __syncthreads();
+    uint32_t rank = 0;
+    if (t < len) {
+      for (int x = 0; x < len; ++x) {
+        if (x != t && sj[x] == j) atomicOr(&bad, 1u);
+        rank += keys[x] < key ? 1u : 0u;
+      }
+    }
+    __syncthreads();  // `bad` is final
+    if (t < len && !bad && key != ~0ull) {
+      const uint64_t e = e0 - qd.ebase + rank;
+      qd.j[e] = j;
+      qd.q[e] = vals[e0 + t];
+      for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+    }
+    if (t == 0) {
+      qd.cnt[q] = bad ? 0u : nz;
+      qd.status[q] = bad ? 1u : 0u;
+    }
+    return;
+  }
   int n = 1;
   while (n < len) n <<= 1;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {

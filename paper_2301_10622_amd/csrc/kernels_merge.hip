@@ -4,6 +4,8 @@
 
 namespace snn {
 
+constexpr uint32_t kRankMax = 1024;  // lists up to this size are ordered by rank counting
+
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
 template <typename T>
@@ -50,6 +52,38 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
     }
     s[e] = src0[(size_t)lo * a.kmax + (e - off[lo])];
   }
+  const bool bad = a.status && a.status[q] != 0u;
+  const uint32_t keep = bad ? 0u : min(M, kq);
+  if (M <= (uint32_t)kRankMax) {
+    // small lists: the keys are distinct (one per document), so each key's
+    // rank is the number of larger keys; the k best go straight to their place
+    __syncthreads();
+    uint64_t *dst = a.groups_out > 1 ? a.out + ((size_t)q * a.groups_out + g) * a.kmax : nullptr;
+    uint32_t *ids = a.res_ids + (size_t)q * a.kmax;
+    float *sc = a.res_scores + (size_t)q * a.kmax;
+    for (uint32_t e = threadIdx.x; e < M; e += blockDim.x) {
+      const uint64_t key = s[e];
+      uint32_t rank = 0;
+      for (uint32_t x = 0; x < M; ++x) rank += s[x] > key ? 1u : 0u;
+      if (rank < keep) {
+        if (dst) {
+          dst[rank] = key;
+        } else {
+          ids[rank] = 0xFFFFFFFFu - (uint32_t)key;
+          sc[rank] = key_value((uint32_t)(key >> 32));
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      if (dst) {
+        a.out_cnt[(size_t)q * a.groups_out + g] = keep;
+      } else {
+        a.res_cnt[q] = keep;
+        if (a.fallback) a.fallback[q] = (!bad && a.keff && M < a.keff[q]) ? 1u : 0u;
+      }
+    }
+    return;
+  }
   for (int e = (int)M + threadIdx.x; e < n; e += blockDim.x) s[e] = 0ull;
   // bitonic sort, descending
   for (int size = 2; size <= n; size <<= 1)
@@ -67,8 +101,6 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
       }
     }
   __syncthreads();
-  const bool bad = a.status && a.status[q] != 0u;
-  const uint32_t keep = bad ? 0u : min(M, kq);
   if (a.groups_out > 1) {
     uint64_t *dst = a.out + ((size_t)q * a.groups_out + g) * a.kmax;
     for (uint32_t e = threadIdx.x; e < keep; e += blockDim.x) dst[e] = s[e];

@@ -143,29 +143,72 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   const cptr<uint32_t> qb = as_const(a.qd.b);
   const cptr<uint64_t> bits = as_const(ix.bits);
   const size_t cap = ix.cap;
-  for (uint32_t c = 0; c < ne; ++c) {
+  // One coordinate of the query: wave-uniform bitmap words in SGPRs, one
+  // 16-byte bound load per lane and group, masked FMAs.
+  auto score_one = [&](uint32_t c) {
     const uint32_t j = qj[e0 + c];
     const float qv = qq[e0 + c];
     const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
     const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
-    if (h == 1) {
-      const __amdgpu_buffer_rsrc_t rs =
-          __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
 #pragma unroll
-      for (int r = 0; r < G; ++r) {
-        const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
-        const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
-        const int off = any ? r * 1024 + lane * 16 : kOob;
-        const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-        const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0));
-        const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
-        const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0));
-        acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v0, acc[4 * r + 0]);
-        acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v1, acc[4 * r + 1]);
-        acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v2, acc[4 * r + 2]);
-        acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v3, acc[4 * r + 3]);
+    for (int r = 0; r < G; ++r) {
+      const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
+      const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
+      const int off = any ? r * 1024 + lane * 16 : kOob;
+      const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+      const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0));
+      const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
+      const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0));
+      acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v0, acc[4 * r + 0]);
+      acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v1, acc[4 * r + 1]);
+      acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v2, acc[4 * r + 2]);
+      acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v3, acc[4 * r + 3]);
+    }
+  };
+  // Two coordinates at a time: their scalar and vector loads are issued
+  // together, so one memory round trip serves both; the adds still go in
+  // coordinate order, so every document's sum is the same as one at a time.
+  auto score_two = [&](uint32_t c) {
+    const uint32_t ja = qj[e0 + c], jb = qj[e0 + c + 1];
+    const float qa = qq[e0 + c], qbv = qq[e0 + c + 1];
+    const cptr<uint64_t> wa = bits + (size_t)ja * ix.W + wword0;
+    const cptr<uint64_t> wb = bits + (size_t)jb * ix.W + wword0;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((qa > 0.0f ? ix.U : ix.L) + wslot0 + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((qbv > 0.0f ? ix.U : ix.L) + wslot0 + (size_t)qb[e0 + c + 1] * cap), 0, G * 1024, kBufFlags);
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const uint64_t a0 = wa[4 * r], a1 = wa[4 * r + 1], a2 = wa[4 * r + 2], a3 = wa[4 * r + 3];
+      const uint64_t b0 = wb[4 * r], b1 = wb[4 * r + 1], b2 = wb[4 * r + 2], b3 = wb[4 * r + 3];
+      const int offa = __builtin_amdgcn_inverse_ballot_w64(a0 | a1 | a2 | a3) ? r * 1024 + lane * 16 : kOob;
+      const int offb = __builtin_amdgcn_inverse_ballot_w64(b0 | b1 | b2 | b3) ? r * 1024 + lane * 16 : kOob;
+      float va[4], vb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        va[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, offa + 4 * i, 0, 0));
+        vb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, offb + 4 * i, 0, 0));
       }
-    } else {
+      const uint64_t aw[4] = {a0, a1, a2, a3}, bw[4] = {b0, b1, b2, b3};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float x = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(aw[i]) ? qa : 0.0f, va[i], acc[4 * r + i]);
+        acc[4 * r + i] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(bw[i]) ? qbv : 0.0f, vb[i], x);
+      }
+    }
+  };
+  if (h == 1) {
+    uint32_t c = 0;
+    for (; c + 1 < ne; c += 2) score_two(c);
+    if (c < ne) score_one(c);
+  } else {
+    for (uint32_t c = 0; c < ne; ++c) {
+      const uint32_t j = qj[e0 + c];
+      const float qv = qq[e0 + c];
+      const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
+      const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
       // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows;
       // unused mappings repeat row 0, which leaves the min / max unchanged
       const bool upper = qv > 0.0f;
