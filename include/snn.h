@@ -125,9 +125,9 @@ typedef enum {
  * uint32) live in device memory; `total` must equal indptr[nq] (the entry
  * count, known to the caller, so the call never reads device memory back).
  * Enqueued on `stream` (NULL: the index stream); the call does not wait for
- * completion except in
- * SNN_MODE_LEARNED, which reads the fallback flags back on the host and
- * re-runs the queries that need the plain path. Malformed queries produce a
+ * completion. In SNN_MODE_LEARNED the queries that need the plain path are
+ * listed and re-run on the device, in the same enqueued work (no host
+ * synchronisation). Malformed queries produce a
  * count of 0 and set the bit in the status returned by snn_last_batch_status.
  * Errors: SNN_E_INVALID (k = 0, nq = 0, mode unknown, no trained filter for
  * SNN_MODE_LEARNED), SNN_E_NOMEM, SNN_E_DEVICE. */
@@ -139,6 +139,23 @@ snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indp
  * (needs the stream synchronised), and, for SNN_MODE_LEARNED, how many fell
  * back to the plain path. */
 snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks);
+
+/* Selection work of the last batch search (both passes of SNN_MODE_LEARNED
+ * counted apart; the *_fallback fields are 0 in the other modes):
+ *   candidates  keys the tiles handed to the merge, i.e. the insertions into
+ *               the top-k selection of Alg. 3 that survived each tile's own
+ *               selection;
+ *   selects     tiles that had more than k keys at or above the query's
+ *               threshold and so ran the radix select (the others pass all
+ *               their keys on without one).
+ * Synchronises the device. */
+typedef struct {
+  uint64_t candidates;
+  uint64_t candidates_fallback;
+  uint64_t selects;
+  uint64_t selects_fallback;
+} snn_batch_work;
+snn_status snn_last_batch_work(snn_index *ix, snn_batch_work *out);
 
 /* Launch schedule of the search kernels. R is the number of slots each lane
  * scores (a workgroup of 256 lanes covers a tile of 256 * R slots); grid is the

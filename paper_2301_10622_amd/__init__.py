@@ -29,7 +29,8 @@ MODE_PLAIN, MODE_BATCHED, MODE_LEARNED = 0, 1, 2
 # every symbol include/snn.h declares (checked by the test suite)
 EXPORTS = [
     "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
-    "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
+    "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
+    "snn_last_batch_work", "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
@@ -93,6 +94,11 @@ class ServeReport(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class BatchWork(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_uint64), ("candidates_fallback", ctypes.c_uint64),
+                ("selects", ctypes.c_uint64), ("selects_fallback", ctypes.c_uint64)]
+
+
 class Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_uint32), ("m", ctypes.c_uint32), ("h", ctypes.c_uint32),
                 ("capacity", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
@@ -121,6 +127,7 @@ def lib():
         L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
         L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
+        L.snn_last_batch_work.argtypes = [P, P]
         L.snn_bucket_table.argtypes = [P, P]
         L.snn_read_sketch.argtypes = [P, u32, P, P]
         L.snn_profile_enable.argtypes = [P, i32]
@@ -141,7 +148,8 @@ def lib():
         L.snn_last_error.argtypes = [P]
         L.snn_last_error.restype = ctypes.c_char_p
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
-                     "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status", "snn_bucket_table",
+                     "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
+                     "snn_last_batch_work", "snn_bucket_table",
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
@@ -268,6 +276,13 @@ class Index:
         self._check(lib().snn_last_batch_status(self._h, ctypes.byref(inv), ctypes.byref(fb)))
         return int(inv.value), int(fb.value)
 
+    def last_batch_work(self):
+        """Selection work of the last batch: candidates handed to the merge and
+        tiles that ran the radix select, main and fallback pass apart."""
+        w = BatchWork()
+        self._check(lib().snn_last_batch_work(self._h, ctypes.byref(w)))
+        return {f: int(getattr(w, f)) for f, _ in BatchWork._fields_}
+
     # ------------------------------------------------------------- timing
     def profile(self, on: bool = True):
         self._check(lib().snn_profile_enable(self._h, 1 if on else 0))
@@ -294,7 +309,7 @@ class Index:
         self._check(lib().snn_get_schedule(self._h, ctypes.byref(sch)))
         return sch.as_dict()
 
-    def set_schedule(self, R_plain=16, R_batch=32, grid=2048, persistent=True):
+    def set_schedule(self, R_plain=16, R_batch=16, grid=2048, persistent=True):
         sch = Schedule(R_plain, R_batch, grid, 1 if persistent else 0, 0.0, 0.0, 0)
         self._check(lib().snn_set_schedule(self._h, ctypes.byref(sch)))
 

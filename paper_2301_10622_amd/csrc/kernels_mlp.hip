@@ -304,101 +304,4 @@ hipError_t launch_threshold(uint32_t nq, const float *yhat, float delta, uint32_
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Fallback compaction: one workgroup scans the flags and builds the CSR of the
-// flagged queries (pos[q] = their rank; new_ptr; sel = original indices).
-// meta[0] = number flagged, meta[1] = their total entries.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fallback_scan(uint32_t nq, const uint32_t *__restrict__ flags,
-                                                       const uint64_t *__restrict__ qptr, uint32_t *__restrict__ sel,
-                                                       uint64_t *__restrict__ new_ptr, uint64_t *__restrict__ meta) {
-  __shared__ uint32_t cnt[256];
-  __shared__ uint64_t len[256];
-  __shared__ uint32_t base_c;
-  __shared__ uint64_t base_e;
-  if (threadIdx.x == 0) {
-    base_c = 0;
-    base_e = 0;
-    new_ptr[0] = 0;
-  }
-  for (uint32_t c0 = 0; c0 < nq; c0 += 256) {
-    const uint32_t q = c0 + threadIdx.x;
-    const uint32_t f = (q < nq && flags[q]) ? 1u : 0u;
-    const uint64_t l = f ? qptr[q + 1] - qptr[q] : 0;
-    cnt[threadIdx.x] = f;
-    len[threadIdx.x] = l;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-      const uint32_t a = threadIdx.x >= (unsigned)d ? cnt[threadIdx.x - d] : 0u;
-      const uint64_t b = threadIdx.x >= (unsigned)d ? len[threadIdx.x - d] : 0u;
-      __syncthreads();
-      cnt[threadIdx.x] += a;
-      len[threadIdx.x] += b;
-      __syncthreads();
-    }
-    if (f) {
-      const uint32_t r = base_c + cnt[threadIdx.x] - 1;
-      sel[r] = q;
-      new_ptr[r + 1] = base_e + len[threadIdx.x];
-    }
-    __syncthreads();
-    if (threadIdx.x == 255) {
-      base_c += cnt[255];
-      base_e += len[255];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    meta[0] = base_c;
-    meta[1] = base_e;
-  }
-}
-
-__global__ void k_fallback_gather(uint32_t n, const uint32_t *__restrict__ sel, const uint64_t *__restrict__ qptr,
-                                  const uint64_t *__restrict__ new_ptr, const uint32_t *__restrict__ c,
-                                  const float *__restrict__ v, uint32_t *__restrict__ oc, float *__restrict__ ov) {
-  const uint32_t r = blockIdx.x;
-  if (r >= n) return;
-  const uint64_t a = qptr[sel[r]], len = qptr[sel[r] + 1] - a, d = new_ptr[r];
-  for (uint64_t e = threadIdx.x; e < len; e += blockDim.x) {
-    oc[d + e] = c[a + e];
-    ov[d + e] = v[a + e];
-  }
-}
-
-__global__ void k_fallback_scatter(uint32_t n, uint32_t k, const uint32_t *__restrict__ sel,
-                                   const uint32_t *__restrict__ ids, const float *__restrict__ sc,
-                                   const uint32_t *__restrict__ cnt, uint32_t *__restrict__ out_ids,
-                                   float *__restrict__ out_sc, uint32_t *__restrict__ out_cnt) {
-  const uint32_t r = blockIdx.x;
-  if (r >= n) return;
-  const uint32_t q = sel[r];
-  for (uint32_t e = threadIdx.x; e < k; e += blockDim.x) {
-    out_ids[(size_t)q * k + e] = ids[(size_t)r * k + e];
-    out_sc[(size_t)q * k + e] = sc[(size_t)r * k + e];
-  }
-  if (threadIdx.x == 0) out_cnt[q] = cnt[r];
-}
-
-hipError_t launch_fallback_scan(uint32_t nq, const uint32_t *flags, const uint64_t *qptr, uint32_t *sel,
-                                uint64_t *new_ptr, uint64_t *meta, hipStream_t s) {
-  hipLaunchKernelGGL(k_fallback_scan, dim3(1), dim3(256), 0, s, nq, flags, qptr, sel, new_ptr, meta);
-  return hipGetLastError();
-}
-
-hipError_t launch_fallback_gather(uint32_t n, const uint32_t *sel, const uint64_t *qptr, const uint64_t *new_ptr,
-                                  const uint32_t *c, const float *v, uint32_t *oc, float *ov, hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fallback_gather, dim3(n), dim3(64), 0, s, n, sel, qptr, new_ptr, c, v, oc, ov);
-  return hipGetLastError();
-}
-
-hipError_t launch_fallback_scatter(uint32_t n, uint32_t k, const uint32_t *sel, const uint32_t *ids, const float *sc,
-                                   const uint32_t *cnt, uint32_t *out_ids, float *out_sc, uint32_t *out_cnt,
-                                   hipStream_t s) {
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fallback_scatter, dim3(n), dim3(64), 0, s, n, k, sel, ids, sc, cnt, out_ids, out_sc, out_cnt);
-  return hipGetLastError();
-}
-
 }  // namespace snn

@@ -324,21 +324,29 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     if (e) {
       const uint32_t pos = basepos + (uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      const uint32_t id = ix.slot2id[slot_of<R>(wslot0, r, lane)];
+      const uint32_t slot = slot_of<R>(wslot0, r, lane);
+      const uint32_t id = ix.slot2id[slot];
       cout[pos] = ((uint64_t)key[r] << 32) | (uint64_t)(0xFFFFFFFFu - id);
+      if (a.cand_slot) a.cand_slot[((size_t)q * a.tiles + t) * a.kmax + pos] = slot;
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     *ccnt = sh.emit;
     if (mode != 0 && T > thr) atomicMax(&a.thr[q], T);
+    if (mode != 0 && a.nselect) atomicAdd(a.nselect, 1ull);
   }
 }
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
   __shared__ SelShared sh;
-  tile_body<R>(a, a.q0 + blockIdx.y, blockIdx.x, sh);
+  uint32_t q = a.q0 + blockIdx.y;
+  if (a.qlist) {
+    if (q >= *as_const(a.nlist)) return;
+    q = as_const(a.qlist)[q];
+  }
+  tile_body<R>(a, q, blockIdx.x, sh);
 }
 
 // Persistent form: a fixed grid pulls (query, tile) items from per-XCD queues.
@@ -352,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
   __shared__ SelShared sh;
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
-  const uint32_t nq = a.nq;
+  const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
   for (uint32_t step = 0; step < X; ++step) {
     const uint32_t x = (home + step) % X;
     const uint32_t tiles_x = a.tiles > x ? (a.tiles - x + X - 1) / X : 0u;
@@ -364,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
       const uint32_t it = sh.item;
       if (it >= items) break;
       const uint32_t t = x + X * (it / nq);
-      const uint32_t q = it % nq;
+      const uint32_t q = a.qlist ? as_const(a.qlist)[it % nq] : it % nq;
       tile_body<R>(a, q, t, sh);
     }
   }

@@ -14,6 +14,7 @@
 #include "snn.h"
 #include "snn_device.h"
 #include "snn_host.h"
+#include "snn_mlp.h"
 
 using namespace snn;
 
@@ -390,6 +391,9 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
   const size_t o_cc2 = o; o += al((size_t)nq * tiles * 4);
   const size_t o_queue = o; o += al(64 * 4);
+  const size_t o_qlist = o; o += al((size_t)nq * 4);
+  const size_t o_nlist = o; o += al(4);
+  const size_t o_stats = o; o += al(32);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
   const uint32_t F = merge_fanin(k);
   const uint32_t g1 = (tiles + F - 1) / F;
@@ -407,6 +411,9 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.cand_cnt = (uint32_t *)(p + o_cc);
   w.cand_cnt2 = (uint32_t *)(p + o_cc2);
   w.queue = (uint32_t *)(p + o_queue);
+  w.qlist = (uint32_t *)(p + o_qlist);
+  w.nlist = (uint32_t *)(p + o_nlist);
+  w.stats = (unsigned long long *)(p + o_stats);
   w.cand = (uint64_t *)W.cand.p;
   w.cand2 = (uint64_t *)W.cand2.p;
   return SNN_OK;
@@ -419,12 +426,10 @@ uint32_t snn_index::merge_fanin(uint32_t k) const {
   return F;
 }
 
-// Enqueue the merge levels for queries [q0, q0 + nqm).
-snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
-                                    uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids,
-                                    float *res_scores, uint32_t *res_cnt, hipStream_t s) {
-  const uint32_t F = merge_fanin(k);
-  uint32_t G = tiles;
+// Enqueue the merge levels of one merge job.
+snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStream_t s) {
+  const uint32_t F = merge_fanin(j.k);
+  uint32_t G = j.tiles;
   const uint64_t *in = w.cand;
   const uint32_t *in_cnt = w.cand_cnt;
   uint64_t *bufs[2] = {w.cand2, w.cand};
@@ -432,30 +437,30 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32
   int lvl = 0;
   for (;;) {
     MergeArgs m{};
-    m.nq = nqm;
-    m.q0 = q0;
     m.groups_in = G;
     m.fanin = std::min(F, G);
     m.groups_out = (G + m.fanin - 1) / m.fanin;
-    m.kmax = k;
-    m.kq = kq;
-    m.keff = keff;
+    m.kmax = j.k;
+    m.kq = j.kq;
+    m.keff = j.keff;
     m.in = in;
     m.in_cnt = in_cnt;
     m.status = w.status;
+    m.qlist = j.qlist;
+    m.nlist = j.nlist;
+    m.emitted = lvl == 0 ? j.emitted : nullptr;
     if (m.groups_out > 1) {
       m.out = bufs[lvl & 1];
       m.out_cnt = cnts[lvl & 1];
     } else {
-      m.res_ids = res_ids;
-      m.res_scores = res_scores;
-      m.res_cnt = res_cnt;
-      m.fallback = w.fallback;
+      m.res_ids = j.res_ids;
+      m.res_scores = j.res_scores;
+      m.res_cnt = j.res_cnt;
+      m.fallback = j.set_fallback ? w.fallback : nullptr;
     }
-    (void)nq_total;
-    for (uint32_t c0 = 0; c0 < nqm; c0 += kMaxGridY) {
-      m.q0 = q0 + c0;
-      m.nq = std::min<uint32_t>(kMaxGridY, nqm - c0);
+    for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
+      m.q0 = j.q0 + c0;
+      m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
       HIP_TRY(this, launch_merge(m, s), "merge kernel");
     }
     if (m.groups_out == 1) break;
@@ -469,16 +474,31 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, uint32_t nq_total, uint32
 
 // Enqueue one batched or plain search. The device work is: query preparation,
 // threshold initialisation, the scoring + selection tiles, the merge levels.
-snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t ev0,
-                                     hipEvent_t ev1) {
+// A learned-filter pass first predicts each query's threshold (features, MLP),
+// and after the filtered merge runs the plain tiles and merge again for the
+// queries that kept fewer than min(k, live) candidates, all on the device.
+// ev (nullable): events around the tile launches (main pass, fallback pass).
+snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t *ev) {
   const SearchWs &w = p.w;
+  const LearnedPass *lp = o.learned;
   QueryDesc qd{p.d_ptr, w.cnt, w.status, w.j, w.q, w.b, o.ebase};
+  if (lp) {
+    HIP_TRY(this, launch_features(p.nq, p.d_ptr, p.d_c, p.d_v, lp->table, lp->dim, lp->X, s), "feature kernel");
+    HIP_TRY(this,
+            launch_mlp_fwd(p.nq, lp->X, nullptr, lp->Pb, lp->yhat, nullptr, 0.0f, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, s),
+            "mlp forward");
+    HIP_TRY(this, launch_threshold(p.nq, lp->yhat, lp->delta, lp->keff_value, lp->thr, lp->keff, s), "threshold");
+  }
   HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, s), "prep kernel");
-  if (o.thr_init) {
-    HIP_TRY(this, launch_copy_u32(w.thr, o.thr_init, p.nq, s), "thr init");
+  const uint32_t *thr_init = lp ? lp->thr : o.thr_init;
+  const uint32_t *keff = lp ? lp->keff : o.keff;
+  if (thr_init) {
+    HIP_TRY(this, launch_copy_u32(w.thr, thr_init, p.nq, s), "thr init");
   } else {
     HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
   }
+  HIP_TRY(this, launch_fill_u32((uint32_t *)w.stats, 0u, 8, s), "stats fill");
   TileArgs a{};
   a.ix = dev;
   a.qd = qd;
@@ -494,6 +514,17 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   a.qseq = o.qseq;
   a.vis = vis;
   a.dirty = dirty;
+  a.nselect = w.stats + 2;
+  MergeJob mj;
+  mj.tiles = p.tiles;
+  mj.k = p.k;
+  mj.kq = o.kq;
+  mj.keff = keff;
+  mj.res_ids = p.d_ids;
+  mj.res_scores = p.d_sc;
+  mj.res_cnt = p.d_cnt;
+  mj.emitted = w.stats;
+  mj.set_fallback = true;
   if (p.mode == SNN_MODE_PLAIN) {
     for (uint32_t q = 0; q < p.nq; ++q) {
       a.q0 = q;
@@ -506,24 +537,48 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
         prof_events.push_back(e0);
         prof_events.push_back(e1);
       }
-      snn_status st = enqueue_merge(w, p.nq, q, 1, p.tiles, p.k, o.kq, o.keff, p.d_ids, p.d_sc, p.d_cnt, s);
+      mj.q0 = q;
+      mj.nqm = 1;
+      snn_status st = enqueue_merge(w, mj, s);
       if (st != SNN_OK) return st;
     }
     return SNN_OK;
   }
-  a.q0 = 0;
-  if (p.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
-  if (ev0) HIP_TRY(this, hipEventRecord(ev0, s), "event");
-  if (p.persistent) {
-    HIP_TRY(this, launch_tiles_persistent(a, p.R, p.grid, s), "persistent tile kernel");
-  } else {
-    for (uint32_t c0 = 0; c0 < p.nq; c0 += kMaxGridY) {
-      a.q0 = c0;
-      HIP_TRY(this, launch_tiles(a, p.R, std::min<uint32_t>(kMaxGridY, p.nq - c0), s), "tile kernel");
+  // one batched tile pass: the persistent grid or one workgroup per item
+  auto tiles_pass = [&](hipEvent_t e0, hipEvent_t e1) -> snn_status {
+    a.q0 = 0;
+    if (p.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
+    if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
+    if (p.persistent) {
+      HIP_TRY(this, launch_tiles_persistent(a, p.R, p.grid, s), "persistent tile kernel");
+    } else {
+      for (uint32_t c0 = 0; c0 < p.nq; c0 += kMaxGridY) {
+        a.q0 = c0;
+        HIP_TRY(this, launch_tiles(a, p.R, std::min<uint32_t>(kMaxGridY, p.nq - c0), s), "tile kernel");
+      }
     }
-  }
-  if (ev1) HIP_TRY(this, hipEventRecord(ev1, s), "event");
-  return enqueue_merge(w, p.nq, 0, p.nq, p.tiles, p.k, o.kq, o.keff, p.d_ids, p.d_sc, p.d_cnt, s);
+    if (e1) HIP_TRY(this, hipEventRecord(e1, s), "event");
+    return SNN_OK;
+  };
+  snn_status st = tiles_pass(ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+  if (st != SNN_OK) return st;
+  mj.q0 = 0;
+  mj.nqm = p.nq;
+  st = enqueue_merge(w, mj, s);
+  if (st != SNN_OK || !lp) return st;
+  // plain fallback of the learned filter, over the flagged queries only
+  HIP_TRY(this, launch_fallback_list(p.nq, w.fallback, w.qlist, w.nlist, w.thr, s), "fallback list");
+  a.qlist = w.qlist;
+  a.nlist = w.nlist;
+  a.nselect = w.stats + 3;
+  st = tiles_pass(ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+  if (st != SNN_OK) return st;
+  mj.keff = nullptr;
+  mj.set_fallback = false;
+  mj.qlist = w.qlist;
+  mj.nlist = w.nlist;
+  mj.emitted = w.stats + 1;
+  return enqueue_merge(w, mj, s);
 }
 
 snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
@@ -556,24 +611,23 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   if (st != SNN_OK) return st;
   if (p.tiles == 0) {  // nothing was ever inserted: no results
     last_status = nullptr;
+    last_stats = nullptr;
+    last_nlist = nullptr;
     HIP_TRY(this, launch_fill_u32(d_cnt, 0u, nq, s), "fill");
     return SNN_OK;
   }
   last_ws = p.w;
   last_status = p.w.status;
+  last_stats = p.w.stats;
+  last_nlist = o.learned ? p.w.nlist : nullptr;
   // graphs need a capturable stream (the legacy default stream is not one);
   // timed (profiled) passes launch eagerly so events can bracket the tile kernel
   if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on || o.no_graph) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (prof_on && mode != SNN_MODE_PLAIN) {
-      e0 = prof_event();
-      e1 = prof_event();
-    }
-    st = enqueue_search(p, o, s, e0, e1);
-    if (e0) {
-      prof_events.push_back(e0);
-      prof_events.push_back(e1);
-    }
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const int nev = prof_on && mode != SNN_MODE_PLAIN ? (o.learned ? 4 : 2) : 0;
+    for (int i = 0; i < nev; ++i) ev[i] = prof_event();
+    st = enqueue_search(p, o, s, nev ? ev : nullptr);
+    for (int i = 0; i < nev; ++i) prof_events.push_back(ev[i]);
     return st;
   }
   // batched forms replay a captured HIP graph of the whole pass
@@ -584,13 +638,18 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
   Workspace &W = o.wsp ? *o.wsp : wsp;
   key.ws = W.ws.p; key.cand = W.cand.p; key.cand2 = W.cand2.p; key.qseq = o.qseq; key.ebase = o.ebase;
+  if (const LearnedPass *lp = o.learned) {
+    key.lX = lp->X; key.ly = lp->yhat; key.lthr = lp->thr; key.lkeff = lp->keff; key.lPb = lp->Pb;
+    key.ltab = lp->table; key.lkeff_v = lp->keff_value;
+    memcpy(&key.ldelta, &lp->delta, 4);
+  }
   GraphEntry *g = graphs.find(key);
   if (!g) {
     GraphEntry e;
     e.key = key;
     hipGraph_t graph = nullptr;
     HIP_TRY(this, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture");
-    snn_status est = enqueue_search(p, o, s, e.ev0, e.ev1);
+    snn_status est = enqueue_search(p, o, s, nullptr);
     hipError_t ce = hipStreamEndCapture(s, &graph);
     if (est != SNN_OK || ce != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -688,14 +747,31 @@ extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uin
 extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {
   if (!ix) return SNN_E_INVALID;
   uint32_t inv = 0;
+  uint32_t fb = 0;
   if (ix->last_nq && ix->last_status) {
     std::vector<uint32_t> st(ix->last_nq);
-    HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
+    HIP_TRY(ix, hipDeviceSynchronize(), "sync");
     HIP_TRY(ix, hipMemcpy(st.data(), ix->last_status, (size_t)ix->last_nq * 4, hipMemcpyDeviceToHost), "status readback");
     for (uint32_t v : st) inv += v != 0;
+    if (ix->last_nlist)
+      HIP_TRY(ix, hipMemcpy(&fb, ix->last_nlist, 4, hipMemcpyDeviceToHost), "fallback count readback");
   }
   if (invalid_queries) *invalid_queries = inv;
-  if (fallbacks) *fallbacks = ix->last_fallbacks;
+  if (fallbacks) *fallbacks = fb;
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_last_batch_work(snn_index *ix, snn_batch_work *out) {
+  if (!ix || !out) return SNN_E_INVALID;
+  unsigned long long c[4] = {0, 0, 0, 0};
+  if (ix->last_nq && ix->last_stats) {
+    HIP_TRY(ix, hipDeviceSynchronize(), "sync");
+    HIP_TRY(ix, hipMemcpy(c, ix->last_stats, 32, hipMemcpyDeviceToHost), "work counters readback");
+  }
+  out->candidates = c[0];
+  out->candidates_fallback = c[1];
+  out->selects = c[2];
+  out->selects_fallback = c[3];
   return SNN_OK;
 }
 

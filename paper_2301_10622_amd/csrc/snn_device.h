@@ -69,6 +69,12 @@ struct TileArgs {
   const uint32_t *qseq;   // [nq] sequence number of each query
   const uint64_t *vis;    // [cap] (insert seq << 32) | delete seq
   const uint64_t *dirty;  // bitmap, slot layout of `live`: slot changed during the session
+  // query list (nullable): the launch covers queries qlist[0 .. *nlist), a count
+  // written on the device by an earlier kernel of the same stream
+  const uint32_t *qlist;
+  const uint32_t *nlist;
+  uint32_t *cand_slot;    // [nq][tiles][kmax] slot of each candidate (nullable)
+  unsigned long long *nselect;  // += 1 per tile that ran the radix select (nullable)
 };
 
 struct MergeArgs {
@@ -89,6 +95,14 @@ struct MergeArgs {
   uint32_t *res_cnt;    // [nq]
   uint32_t *fallback;   // [nq] set to 1 when fewer than keff candidates survived
   const uint32_t *status; // [nq] malformed queries produce 0 results
+  const uint32_t *qlist;  // query list (nullable), as in TileArgs
+  const uint32_t *nlist;
+  unsigned long long *emitted; // first level only (nullable): += candidates read
+  // candidate slots carried with the keys (nullable): in / out per level, and
+  // the final level's [nq][kmax] slots of the results
+  const uint32_t *in_slot;
+  uint32_t *out_slot;
+  uint32_t *res_slots;
 };
 
 __host__ __device__ inline uint32_t slot_word(uint32_t slot) { return ((slot >> 8) << 2) | (slot & 3u); }
@@ -119,5 +133,7 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStre
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t s);
+hipError_t launch_fallback_list(uint32_t nq, const uint32_t *flags, uint32_t *qlist, uint32_t *nlist, uint32_t *thr,
+                                hipStream_t s);
 
 }  // namespace snn

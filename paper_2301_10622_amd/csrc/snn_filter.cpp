@@ -25,11 +25,11 @@ struct LearnedFilter {
   bool table_ok = false;
   uint32_t adam_t = 0;
   DevBuf P, Pb, M, V, G, table;
-  DevBuf X, yhat, thr, keff, sel, newptr, meta, fb_c, fb_v, fb_out, stat;  // search scratch
+  DevBuf X, yhat, thr, keff;                                          // search scratch
   DevBuf tX, ty, trow, tyrow, H1, H2, D1, D2, DY, loss, tmpy;        // training scratch
   void release() {
-    for (DevBuf *b : {&P, &Pb, &M, &V, &G, &table, &X, &yhat, &thr, &keff, &sel, &newptr, &meta, &fb_c, &fb_v,
-                      &fb_out, &stat, &tX, &ty, &trow, &tyrow, &H1, &H2, &D1, &D2, &DY, &loss, &tmpy})
+    for (DevBuf *b : {&P, &Pb, &M, &V, &G, &table, &X, &yhat, &thr, &keff, &tX, &ty, &trow, &tyrow, &H1, &H2, &D1,
+                      &D2, &DY, &loss, &tmpy})
       b->release();
   }
 };
@@ -357,59 +357,23 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
                                      hipStream_t s) {
   LearnedFilter *f = filter;
   if (!f || !f->ready) return fail(SNN_E_INVALID, "search: no trained filter (call snn_filter_train first)");
+  HIP_TRY(this, f->X.ensure((size_t)nq * kFeat * 4, s), "features");
   HIP_TRY(this, f->yhat.ensure((size_t)nq * 4, s), "yhat");
   HIP_TRY(this, f->thr.ensure((size_t)nq * 4, s), "thr");
   HIP_TRY(this, f->keff.ensure((size_t)nq * 4, s), "keff");
-  HIP_TRY(this, f->sel.ensure((size_t)nq * 4, s), "sel");
-  HIP_TRY(this, f->newptr.ensure((size_t)(nq + 1) * 8, s), "newptr");
-  HIP_TRY(this, f->meta.ensure(64, s), "meta");
-  snn_status st = predict(this, f, nq, d_ptr, d_c, d_v, (float *)f->yhat.p, s);
-  if (st != SNN_OK) return st;
-  const uint32_t keff = (uint32_t)std::min<size_t>(k, live);
-  HIP_TRY(this, launch_threshold(nq, (float *)f->yhat.p, f->delta, keff, (uint32_t *)f->thr.p, (uint32_t *)f->keff.p, s),
-          "threshold");
+  LearnedPass lp;
+  lp.table = (const uint32_t *)f->table.p;
+  lp.Pb = (const uint16_t *)f->Pb.p;
+  lp.X = (float *)f->X.p;
+  lp.yhat = (float *)f->yhat.p;
+  lp.thr = (uint32_t *)f->thr.p;
+  lp.keff = (uint32_t *)f->keff.p;
+  lp.delta = f->delta;
+  lp.keff_value = (uint32_t)std::min<size_t>(k, live);
+  lp.dim = cfg.dim;
   SearchOpts o;
-  o.thr_init = (const uint32_t *)f->thr.p;
-  o.keff = (const uint32_t *)f->keff.p;
-  st = run_search(nq, d_ptr, total, d_c, d_v, k, SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, o);
-  if (st != SNN_OK) return st;
-  if (!last_status) {  // empty index: nothing to check
-    last_fallbacks = 0;
-    return SNN_OK;
-  }
-  // keep this batch's per-query status: the fallback pass below reuses the workspace
-  HIP_TRY(this, f->stat.ensure((size_t)nq * 4, s), "status copy");
-  HIP_TRY(this, launch_copy_u32((uint32_t *)f->stat.p, last_status, nq, s), "status copy");
-  // queries whose filter let fewer than min(k, live) documents through run again, plain
-  HIP_TRY(this,
-          launch_fallback_scan(nq, last_ws.fallback, d_ptr, (uint32_t *)f->sel.p, (uint64_t *)f->newptr.p,
-                               (uint64_t *)f->meta.p, s),
-          "fallback scan");
-  uint64_t meta[2] = {0, 0};
-  HIP_TRY(this, hipMemcpyAsync(meta, f->meta.p, 16, hipMemcpyDeviceToHost, s), "fallback count");
-  HIP_TRY(this, hipStreamSynchronize(s), "fallback sync");
-  last_fallbacks = (uint32_t)meta[0];
-  last_status = (const uint32_t *)f->stat.p;
-  if (meta[0] == 0) return SNN_OK;
-  const uint32_t n = (uint32_t)meta[0];
-  const uint64_t ne = meta[1];
-  HIP_TRY(this, f->fb_c.ensure(ne * 4 + 16, s), "fallback entries");
-  HIP_TRY(this, f->fb_v.ensure(ne * 4 + 16, s), "fallback entries");
-  HIP_TRY(this, f->fb_out.ensure((size_t)n * k * 8 + (size_t)n * 4 + 256, s), "fallback results");
-  HIP_TRY(this,
-          launch_fallback_gather(n, (uint32_t *)f->sel.p, d_ptr, (uint64_t *)f->newptr.p, d_c, d_v,
-                                 (uint32_t *)f->fb_c.p, (float *)f->fb_v.p, s),
-          "fallback gather");
-  uint32_t *fid = (uint32_t *)f->fb_out.p;
-  float *fsc = (float *)(fid + (size_t)n * k);
-  uint32_t *fcnt = (uint32_t *)(fsc + (size_t)n * k);
-  st = run_search(n, (uint64_t *)f->newptr.p, ne, (uint32_t *)f->fb_c.p, (float *)f->fb_v.p, k, SNN_MODE_BATCHED, fid,
-                  fsc, fcnt, s, SearchOpts{});
-  if (st != SNN_OK) return st;
-  HIP_TRY(this, launch_fallback_scatter(n, k, (uint32_t *)f->sel.p, fid, fsc, fcnt, d_ids, d_sc, d_cnt, s),
-          "fallback scatter");
-  last_status = (const uint32_t *)f->stat.p;
-  return SNN_OK;
+  o.learned = &lp;
+  return run_search(nq, d_ptr, total, d_c, d_v, k, SNN_MODE_LEARNED, d_ids, d_sc, d_cnt, s, o);
 }
 
 void snn_filter_release(snn_index *ix) {

@@ -44,20 +44,34 @@ struct SearchWs {
   float *q = nullptr;
   uint32_t *cand_cnt = nullptr, *cand_cnt2 = nullptr, *queue = nullptr;
   uint64_t *cand = nullptr, *cand2 = nullptr;
+  uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
+  unsigned long long *stats = nullptr;          // candidates emitted, selecting tiles (main, fallback pass)
 };
 
 // Launch schedule of the search kernels (set by the autotuner).
 struct Tune {
   int R_plain = 16;      // registers (64-doc groups) per lane, plain mode
-  int R_batch = 32;      // same, batched mode
+  int R_batch = 16;      // same, batched mode
   bool persistent = true;
   uint32_t grid = 2048;  // persistent grid
 };
 
 struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
 
+// Device state of a learned-filter pass: feature table and bf16 weights, per-query
+// features, prediction, threshold keys and required counts.
+struct LearnedPass {
+  const uint32_t *table = nullptr;
+  const uint16_t *Pb = nullptr;
+  float *X = nullptr, *yhat = nullptr;
+  uint32_t *thr = nullptr, *keff = nullptr;
+  float delta = 0.0f;
+  uint32_t keff_value = 0, dim = 0;
+};
+
 // Optional per-query inputs of a search (device arrays of nq entries).
 struct SearchOpts {
+  const LearnedPass *learned = nullptr;  // filtered pass with a device-side plain fallback
   const uint32_t *thr_init = nullptr;  // initial inclusive threshold keys (learned filter)
   const uint32_t *kq = nullptr;        // per-query k (<= the batch k)
   const uint32_t *keff = nullptr;      // count below which the filter check reports a fallback
@@ -65,6 +79,18 @@ struct SearchOpts {
   uint64_t ebase = 0;                  // indptr value of the batch's first entry
   Workspace *wsp = nullptr;            // buffers (null: the index's own)
   bool no_graph = false;
+};
+
+// One merge pass (all levels) over the tile candidates of queries q0 .. q0 + nqm
+// (or of the listed queries, when qlist is set).
+struct MergeJob {
+  uint32_t q0 = 0, nqm = 0, tiles = 0, k = 0;
+  const uint32_t *kq = nullptr, *keff = nullptr;
+  uint32_t *res_ids = nullptr, *res_cnt = nullptr, *res_slots = nullptr;
+  float *res_scores = nullptr;
+  const uint32_t *qlist = nullptr, *nlist = nullptr;
+  unsigned long long *emitted = nullptr;
+  bool set_fallback = false;
 };
 
 struct SearchPlan {
@@ -85,10 +111,14 @@ struct GraphKey {
   uint64_t total;
   bool persistent, prof;
   const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2, *qseq;
+  const void *lX, *ly, *lthr, *lkeff, *lPb, *ltab;
+  uint32_t ldelta, lkeff_v;
   uint64_t ebase;
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
+           lX == o.lX && ly == o.ly && lthr == o.lthr && lkeff == o.lkeff && lPb == o.lPb && ltab == o.ltab &&
+           ldelta == o.ldelta && lkeff_v == o.lkeff_v &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
            ws == o.ws && cand == o.cand && cand2 == o.cand2 && qseq == o.qseq && ebase == o.ebase &&
@@ -159,8 +189,10 @@ struct snn_index {
   uint64_t *vis = nullptr, *dirty = nullptr;  // serving snapshot state (allocated by snn_serve_run)
   snn::PinBuf pin;
   snn::SearchWs last_ws;
-  uint32_t last_nq = 0, last_mode = 0, last_fallbacks = 0;
+  uint32_t last_nq = 0, last_mode = 0;
   const uint32_t *last_status = nullptr;  // device: per-query status of the last batch
+  const uint32_t *last_nlist = nullptr;   // device: fallback count of the last learned batch
+  const unsigned long long *last_stats = nullptr;  // device: selection work of the last batch
   snn::Tune tune;
   snn::LearnedFilter *filter = nullptr;
 
@@ -191,14 +223,11 @@ struct snn_index {
   snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, snn::SearchWs &w,
                                snn::Workspace &W, hipStream_t s);
   uint32_t merge_fanin(uint32_t k) const;
-  snn_status enqueue_merge(const snn::SearchWs &w, uint32_t nq_total, uint32_t q0, uint32_t nqm, uint32_t tiles,
-                           uint32_t k, const uint32_t *kq, const uint32_t *keff, uint32_t *res_ids, float *res_scores,
-                           uint32_t *res_cnt, hipStream_t s);
+  snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
                          uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p,
                          const snn::SearchOpts &o, hipStream_t s);
-  snn_status enqueue_search(const snn::SearchPlan &p, const snn::SearchOpts &o, hipStream_t s, hipEvent_t ev0,
-                            hipEvent_t ev1);
+  snn_status enqueue_search(const snn::SearchPlan &p, const snn::SearchOpts &o, hipStream_t s, hipEvent_t *ev);
   snn_status run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s,
                         const snn::SearchOpts &o);

@@ -28,12 +28,5 @@ hipError_t launch_to_bf16(const float *P, uint16_t *Pb, uint32_t n, hipStream_t 
 hipError_t launch_labels(uint32_t nq, uint32_t k, const float *scores, const uint32_t *cnt, float *y, hipStream_t s);
 hipError_t launch_threshold(uint32_t nq, const float *yhat, float delta, uint32_t keff, uint32_t *thr, uint32_t *ke,
                             hipStream_t s);
-hipError_t launch_fallback_scan(uint32_t nq, const uint32_t *flags, const uint64_t *qptr, uint32_t *sel,
-                                uint64_t *new_ptr, uint64_t *meta, hipStream_t s);
-hipError_t launch_fallback_gather(uint32_t n, const uint32_t *sel, const uint64_t *qptr, const uint64_t *new_ptr,
-                                  const uint32_t *c, const float *v, uint32_t *oc, float *ov, hipStream_t s);
-hipError_t launch_fallback_scatter(uint32_t n, uint32_t k, const uint32_t *sel, const uint32_t *ids, const float *sc,
-                                   const uint32_t *cnt, uint32_t *out_ids, float *out_sc, uint32_t *out_cnt,
-                                   hipStream_t s);
 
 }  // namespace snn

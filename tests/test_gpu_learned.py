@@ -124,6 +124,111 @@ def test_learned_results_identical_to_plain(trained, k):
         assert fb <= 0.15 * 2048, fb  # calibrated for about 5%
 
 
+def _work(ix):
+    w = ix.last_batch_work()
+    return w["candidates"] + w["candidates_fallback"], w["selects"] + w["selects_fallback"]
+
+
+@pytest.fixture(scope="module")
+def trained100():
+    import paper_2301_10622_amd as P
+
+    w = gen.make_small(0)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
+    ix.set_schedule(R_plain=16, R_batch=16, grid=2048, persistent=True)  # tiles of 4,096 slots
+    P.load_docs(ix, w.docs)
+    tq = gen.small_queries(2, 20000)
+    rep = ix.filter_train(*_dev(tq), k=100, epochs=6, batch=512, lr=1e-3, feature_seed=FSEED)
+    yield ix, rep
+    ix.close()
+
+
+def test_what_the_trained_network_gains(trained100):
+    """The filter exists to cut insertions into the top-k selection: only
+    documents scoring >= tau reach it. For 1,024 queries (k = 100) count, from
+    the oracle's FP64 scores, how many documents pass tau = exp(yhat - delta)
+    of the trained network, and how many pass the best constant predictor, one
+    tau for all queries set so that the same share of queries falls back
+    (fewer than k pass). At equal fallback the trained network lets through a
+    small fraction of what the constant does. On the GPU the same three
+    searches (no filter, trained, constant) give identical results, and the
+    counters of the tiles that ran the radix select follow the same order."""
+    import paper_2301_10622_amd as P
+
+    ix, rep = trained100
+    n, k = 1024, 100
+    w = gen.make_small(0)
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    q = gen.small_queries(3, n)
+    t = _dev(q)
+    yhat = ix.filter_predict(*t).cpu().numpy().astype(np.float64)
+    tau = np.exp(yhat - rep["delta"]).astype(np.float32).astype(np.float64)
+    scores = [ora.score_all(*q.row(i))[0] for i in range(n)]
+    sk = np.array([np.sort(sc)[-k] for sc in scores])
+    passed = np.array([(sc >= tt).sum() for sc, tt in zip(scores, tau)])
+    fb = passed < k
+    # the constant threshold with the same number of fallbacks
+    tc = np.sort(sk)[int(fb.sum())]
+    passed_c = np.array([(sc >= tc).sum() for sc in scores])
+    print("documents passing per query: trained mean %.0f (%d fallbacks), constant mean %.0f (%d fallbacks)"
+          % (passed[~fb].mean(), fb.sum(), passed_c[passed_c >= k].mean(), (passed_c < k).sum()))
+    assert abs(int((passed_c < k).sum()) - int(fb.sum())) <= 2
+    assert fb.mean() <= 0.15
+    assert passed[~fb].mean() < 0.5 * passed_c[passed_c >= k].mean()
+
+    # the three forms on the GPU: identical results, selection work in that order
+    plain = _dev_search(ix, t, k, P.MODE_BATCHED)
+    c_plain, s_plain = _work(ix)
+    learned = _dev_search(ix, t, k, P.MODE_LEARNED)
+    c_learned, s_learned = _work(ix)
+    params = ix.filter_get_params()
+    try:
+        const = np.zeros(P.MLP_PARAMS, np.float32)
+        const[-1] = np.log(tc)
+        ix.filter_set_params(const, FSEED, k)
+        ix.filter_set_delta(0.0)
+        constant = _dev_search(ix, t, k, P.MODE_LEARNED)
+        c_const, s_const = _work(ix)
+    finally:
+        ix.filter_set_params(params, FSEED, k)
+        ix.filter_set_delta(rep["delta"])
+    for a, b, c in zip(plain, learned, constant):
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+    print("GPU selects / candidates: no filter %d / %d, trained %d / %d, constant %d / %d"
+          % (s_plain, c_plain, s_learned, c_learned, s_const, c_const))
+    assert s_learned < s_plain and s_learned < s_const
+
+
+def test_learned_graph_replays_match_eager(trained):
+    """On a capturable stream the whole learned pass (features, MLP, threshold,
+    filtered tiles, merge, fallback list, plain re-run) is one HIP graph; every
+    replay, with eager work in between, equals the unfiltered batched result."""
+    import torch
+    import paper_2301_10622_amd as P
+
+    w, ix, rep = trained
+    t = _dev(gen.small_queries(6, 700))
+    ref = _dev_search(ix, t, 10, P.MODE_BATCHED)
+    dev = torch.device("cuda:0")
+    out = (torch.empty((700, 10), dtype=torch.int32, device=dev), torch.empty((700, 10), dtype=torch.float32, device=dev),
+           torch.empty(700, dtype=torch.int32, device=dev))
+    stream = torch.cuda.Stream()
+    fbs = []
+    for it in range(4):
+        for o in out:
+            o.fill_(-1)
+        torch.cuda.synchronize()
+        ix.search_batch_dev(*t, 10, mode=P.MODE_LEARNED, out=out, stream=stream)
+        stream.synchronize()
+        got = tuple(o.cpu().numpy() for o in out)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), it
+        fbs.append(ix.last_batch_status()[1])
+        # eager work between replays
+        _dev_search(ix, t, 10, P.MODE_BATCHED)
+    assert len(set(fbs)) == 1 and fbs[0] > 0, fbs
+
+
 def test_forced_fallback_and_pass_all(trained):
     import paper_2301_10622_amd as P
 
