@@ -62,6 +62,7 @@ def lib():
         L.orc_find_largest.restype = u32
         L.orc_find_largest.argtypes = [u32, P, P, P, u32, P]
         L.orc_search.argtypes = [P, u32, P, P, P, u32, i32, i32, P, P, P, P]
+        L.orc_rerank.argtypes = [P, u32, P, P, P, u32, u32, i32, P, P, P, P]
         L.orc_max_threads.restype = i32
         L.orc_features.argtypes = [u32, P, P, u64, P]
         L.orc_mlp_forward.argtypes = [u32, P, P, P, P, P, P, P, P]
@@ -178,6 +179,18 @@ class Index:
         cnt = np.zeros(nq, dtype=np.uint32)
         lib().orc_search(self._h, nq, _p(qp), _p(qc), _p(qv), k, 1 if exact else 0, threads,
                          _p(ids), _p(sc), _p(ab), _p(cnt))
+        return ids[:, :k], sc[:, :k], ab[:, :k], cnt
+
+    def rerank(self, queries, k: int, kprime: int, threads: int = 1):
+        """Alg. 7 with k' >= k: (ids, exact scores, sum |q_j x_j|, counts)."""
+        qp = np.ascontiguousarray(queries.indptr, dtype=np.int64)
+        qc, qv = _u32(queries.coords), _f32(queries.vals)
+        nq = len(qp) - 1
+        ids = np.zeros((nq, max(k, 1)), dtype=np.uint32)
+        sc = np.zeros((nq, max(k, 1)))
+        ab = np.zeros((nq, max(k, 1)))
+        cnt = np.zeros(nq, dtype=np.uint32)
+        lib().orc_rerank(self._h, nq, _p(qp), _p(qc), _p(qv), k, kprime, threads, _p(ids), _p(sc), _p(ab), _p(cnt))
         return ids[:, :k], sc[:, :k], ab[:, :k], cnt
 
 

@@ -24,6 +24,9 @@
  *   - exact scoring (Eq. 2 via Alg. 2): the same walk with the true value x_i[j].
  *   - ranking with k' = k (Alg. 7 reduces to Alg. 3): FindLargest with a binary
  *     heap. Ties at equal score are broken by the lower external id.
+ *   - ranking with k' >= k (Alg. 7): FindLargest(k') over the estimates, the
+ *     exact inner product of each of those k' vectors fetched from the vector
+ *     storage, FindLargest(k) over the exact scores.
  *   - the small MLP of the learned threshold filter (not in the paper): dense
  *     layers in FP64 with ReLU, mean squared error, plain back-propagation.
  *
@@ -232,6 +235,9 @@ typedef struct {
   float *list_val;    /* the true values, used only by exact scoring */
   double *U, *L;      /* sketch matrix halves, m rows of N columns */
   uint32_t *ids;      /* external id of every position */
+  int64_t *vec_ptr;   /* vector storage S of Alg. 7: the documents as given */
+  uint32_t *vec_c;
+  float *vec_v;
 } orc_index;
 
 orc_index *orc_build(uint32_t N, const int64_t *indptr, const uint32_t *coords, const float *vals,
@@ -276,6 +282,16 @@ orc_index *orc_build(uint32_t N, const int64_t *indptr, const uint32_t *coords, 
   free(u);
   free(l);
   free(fill);
+  /* the vector storage keeps every document's (coordinate, value) pairs */
+  size_t E = (size_t)(indptr[N] - indptr[0]);
+  ix->vec_ptr = (int64_t *)malloc(sizeof(int64_t) * ((size_t)N + 1));
+  ix->vec_c = (uint32_t *)malloc(sizeof(uint32_t) * (E ? E : 1));
+  ix->vec_v = (float *)malloc(sizeof(float) * (E ? E : 1));
+  for (uint32_t i = 0; i <= N; ++i) ix->vec_ptr[i] = indptr[i] - indptr[0];
+  if (E) {
+    memcpy(ix->vec_c, coords + indptr[0], sizeof(uint32_t) * E);
+    memcpy(ix->vec_v, vals + indptr[0], sizeof(float) * E);
+  }
   return ix;
 }
 
@@ -287,6 +303,9 @@ void orc_free(orc_index *ix) {
   free(ix->U);
   free(ix->L);
   free(ix->ids);
+  free(ix->vec_ptr);
+  free(ix->vec_c);
+  free(ix->vec_v);
   free(ix);
 }
 
@@ -426,6 +445,61 @@ void orc_search(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uin
     free(sc);
     free(ab);
     free(pos);
+  }
+}
+
+/* Ranking with k' >= k (Alg. 7) for a batch of queries. Per query: the
+ * Sinnamon scores of every document (Alg. 6); V = FindLargest(scores, k');
+ * s_v = <q, S.Fetch(v)> for v in V, the exact inner product (Eq. 2) of the
+ * query with the stored vector; the result is FindLargest({s_v}, k). Both
+ * FindLargest calls break ties by the lower external id. out_scores are the
+ * exact scores s_v, out_abs the sums of |q_j x_j| over the shared coordinates
+ * (the error scale of the comparison tolerance); counts = min(k, k', N). */
+void orc_rerank(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uint32_t *qc, const float *qv,
+                uint32_t k, uint32_t kprime, int threads, uint32_t *out_ids, double *out_scores, double *out_abs,
+                uint32_t *out_counts) {
+#ifdef _OPENMP
+  if (threads < 1) threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+#endif
+  for (int64_t qi = 0; qi < (int64_t)nq; ++qi) {
+    double *sc = (double *)malloc(sizeof(double) * (ix->N ? ix->N : 1));
+    uint32_t *V = (uint32_t *)malloc(sizeof(uint32_t) * (kprime ? kprime : 1));
+    double *sv = (double *)malloc(sizeof(double) * (kprime ? kprime : 1));
+    double *av = (double *)malloc(sizeof(double) * (kprime ? kprime : 1));
+    uint32_t *vid = (uint32_t *)malloc(sizeof(uint32_t) * (kprime ? kprime : 1));
+    uint32_t *best = (uint32_t *)malloc(sizeof(uint32_t) * (k ? k : 1));
+    int64_t a = qptr[qi], b = qptr[qi + 1];
+    uint32_t qn = (uint32_t)(b - a);
+    orc_score_all(ix, qn, qc + a, qv + a, 0, sc, NULL);
+    uint32_t nv = orc_find_largest(ix->N, sc, ix->ids, NULL, kprime, V);
+    for (uint32_t r = 0; r < nv; ++r) {
+      uint32_t d = V[r];
+      int64_t d0 = ix->vec_ptr[d], d1 = ix->vec_ptr[d + 1];
+      sv[r] = orc_pair_exact(qn, qc + a, qv + a, (uint32_t)(d1 - d0), ix->vec_c + d0, ix->vec_v + d0);
+      /* |q_j x_j| summed over the coordinates both vectors hold */
+      double s_abs = 0.0;
+      for (uint32_t t = 0; t < qn; ++t) {
+        if (qv[a + t] == 0.0f) continue;
+        int p = orc_find((uint32_t)(d1 - d0), ix->vec_c + d0, qc[a + t]);
+        if (p >= 0) s_abs += fabs((double)qv[a + t] * (double)ix->vec_v[d0 + p]);
+      }
+      av[r] = s_abs;
+      vid[r] = ix->ids[d];
+    }
+    uint32_t c = orc_find_largest(nv, sv, vid, NULL, k, best);
+    out_counts[qi] = c;
+    for (uint32_t r = 0; r < c; ++r) {
+      out_ids[(size_t)qi * k + r] = vid[best[r]];
+      out_scores[(size_t)qi * k + r] = sv[best[r]];
+      out_abs[(size_t)qi * k + r] = av[best[r]];
+    }
+    free(sc);
+    free(V);
+    free(sv);
+    free(av);
+    free(vid);
+    free(best);
   }
 }
 

@@ -300,6 +300,72 @@ def test_search_equals_score_all_then_select(small):
 
 
 # --------------------------------------------------------------------------
+# ranking with k' >= k (Alg. 7)
+# --------------------------------------------------------------------------
+
+def _dense(w):
+    D = np.zeros((w.docs.rows, w.n))
+    for i in range(w.docs.rows):
+        c, v = w.docs.row(i)
+        D[i, c] = v
+    return D
+
+
+def _dense_q(w, qi):
+    qc, qv = w.queries.row(qi)
+    q = np.zeros(w.n)
+    q[qc] = qv
+    return qc, qv, q
+
+
+def test_rerank_equals_brute_force_composition(small):
+    """Alg. 7 written out with a dense matrix product and a plain sort: the k'
+    best estimates (ties to the lower id), their exact inner products, the k
+    best of those. Also returns |q_j x_j| summed over shared coordinates."""
+    w, ix = small
+    D = _dense(w)
+    ids_all = np.arange(w.docs.rows)
+    for k, kp in ((10, 10), (10, 57), (5, 300), (25, 1000)):
+        ids, sc, ab, cnt = ix.rerank(w.queries, k, kp, threads=4)
+        for qi in range(w.queries.rows):
+            qc, qv, q = _dense_q(w, qi)
+            est, _ = ix.score_all(qc, qv)
+            V = _brute_topk(est, ids_all, kp)
+            ex = D[V] @ q
+            best = [V[p] for p in _brute_topk(ex, np.array(V), k)]
+            assert list(ids[qi][: cnt[qi]]) == best, (k, kp, qi)
+            np.testing.assert_allclose(sc[qi][: cnt[qi]], D[best] @ q, rtol=1e-12, atol=1e-12)
+            np.testing.assert_allclose(ab[qi][: cnt[qi]], np.abs(D[best] * q).sum(axis=1), rtol=1e-12, atol=1e-12)
+
+
+def test_rerank_of_every_vector_is_exact_search(small):
+    """With k' at least the collection size, re-ranking scores every vector
+    exactly, so the result is the exact top-k of Eq. 2."""
+    w, ix = small
+    D = _dense(w)
+    ids, sc, ab, cnt = ix.rerank(w.queries, 10, w.docs.rows + 5)
+    for qi in range(w.queries.rows):
+        _, _, q = _dense_q(w, qi)
+        assert list(ids[qi]) == _brute_topk(D @ q, np.arange(w.docs.rows), 10)
+
+
+def test_rerank_recall_never_drops_as_kprime_grows(small):
+    """The candidate sets are nested in k', and a vector of the exact top-k
+    that is a candidate stays in the re-ranked top-k, so recall against the
+    exact top-k cannot fall as k' grows; at k' = N it is 1."""
+    w, ix = small
+    D = _dense(w)
+    truth = [set(_brute_topk(D @ _dense_q(w, qi)[2], np.arange(w.docs.rows), 10)) for qi in range(w.queries.rows)]
+    prev = np.zeros(w.queries.rows)
+    for kp in (10, 20, 50, 100, 400, 2000):
+        ids, _, _, cnt = ix.rerank(w.queries, 10, kp)
+        rec = np.array([len(truth[qi] & set(ids[qi][: cnt[qi]].tolist())) / 10 for qi in range(w.queries.rows)])
+        assert np.all(rec >= prev), kp
+        prev = rec
+    assert np.all(prev == 1.0)
+
+
+# --------------------------------------------------------------------------
 # MLP of the learned filter: gradients against central differences
 # --------------------------------------------------------------------------
 
