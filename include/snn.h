@@ -59,7 +59,11 @@ typedef enum {
  *             2014); the paper leaves the mappings unspecified
  *   capacity  maximum number of live documents (document slots); rounded up
  *             to a multiple of 16384 internally
- *   flags     reserved, must be 0 */
+ *   flags     0 or SNN_FORWARD_STORE */
+/* Keep every live document's (coordinate, value) pairs on the device as well:
+ * the vector storage S of Alg. 7, which the re-ranking search reads. Costs
+ * 8 bytes per non-zero in HBM and the matching upload on insert. */
+#define SNN_FORWARD_STORE 1u
 typedef struct {
   uint32_t dim;
   uint32_t m;
@@ -134,6 +138,24 @@ typedef enum {
 snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
                                 const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
                                 float *out_scores, uint32_t *out_counts, void *stream);
+
+/* Ranking with k' >= k (Alg. 7): the k_prime documents with the largest
+ * Sinnamon scores are fetched from the forward store, scored exactly (the
+ * inner product of Eq. 2, FP32 sums) and the k best by exact score are
+ * returned, ties by the lower external id. out_scores hold those exact
+ * scores. Needs an index created with SNN_FORWARD_STORE. Device pointers and
+ * stream as in snn_search_batch_dev; outputs are nq x k and nq counts of
+ * min(k, k_prime, live). Errors: SNN_E_INVALID (no forward store, k = 0,
+ * k_prime < k or k_prime > 4096, nq = 0), SNN_E_NOMEM, SNN_E_DEVICE. */
+snn_status snn_search_rerank_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                 const uint32_t *coords, const float *vals, uint32_t k, uint32_t k_prime,
+                                 uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream);
+
+/* The same from host buffers (CSR queries as in snn_search_batch); returns
+ * after the results are on the host. */
+snn_status snn_search_rerank(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                             const float *vals, uint32_t k, uint32_t k_prime, uint32_t *out_ids, float *out_scores,
+                             uint32_t *out_counts);
 
 /* Number of queries of the last snn_search_batch_dev call that were malformed
  * (needs the stream synchronised), and, for SNN_MODE_LEARNED, how many fell

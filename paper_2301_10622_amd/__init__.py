@@ -25,12 +25,13 @@ SNN_OK = 0
 STATUS = {0: "SNN_OK", -1: "SNN_E_INVALID", -2: "SNN_E_EXISTS", -3: "SNN_E_NOT_FOUND", -4: "SNN_E_FULL",
           -5: "SNN_E_NOMEM", -6: "SNN_E_BUSY", -7: "SNN_E_DEVICE"}
 MODE_PLAIN, MODE_BATCHED, MODE_LEARNED = 0, 1, 2
+FORWARD_STORE = 1  # snn_config.flags: keep the vectors on the device (re-ranking, Alg. 7)
 
 # every symbol include/snn.h declares (checked by the test suite)
 EXPORTS = [
     "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
     "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
-    "snn_last_batch_work", "snn_bucket_table",
+    "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
@@ -127,6 +128,8 @@ def lib():
         L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
         L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
+        L.snn_search_rerank.argtypes = [P, u32, P, P, P, u32, u32, P, P, P]
+        L.snn_search_rerank_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_work.argtypes = [P, P]
         L.snn_bucket_table.argtypes = [P, P]
         L.snn_read_sketch.argtypes = [P, u32, P, P]
@@ -149,7 +152,7 @@ def lib():
         L.snn_last_error.restype = ctypes.c_char_p
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
-                     "snn_last_batch_work", "snn_bucket_table",
+                     "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_bucket_table",
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
@@ -176,9 +179,10 @@ def _stream_handle(stream) -> ctypes.c_void_p:
 class Index:
     """A device-resident Sinnamon index (owns its device memory)."""
 
-    def __init__(self, dim: int, m: int, h: int = 1, capacity: int = 1 << 16, hash_seed: int = 0, stream=None):
+    def __init__(self, dim: int, m: int, h: int = 1, capacity: int = 1 << 16, hash_seed: int = 0, stream=None,
+                 forward_store: bool = False):
         L = lib()
-        self._cfg = Config(dim, m, h, capacity, hash_seed, 0, 0)
+        self._cfg = Config(dim, m, h, capacity, hash_seed, FORWARD_STORE if forward_store else 0, 0)
         self.dim, self.m, self.h = dim, m, h
         h_ptr = ctypes.c_void_p()
         if stream is None and torch is not None and torch.cuda.is_available():
@@ -248,6 +252,37 @@ class Index:
         sc = np.zeros((nq, k), np.float32)
         cnt = np.zeros(nq, np.uint32)
         self._check(lib().snn_search_batch(self._h, nq, _p(ip), _p(c), _p(v), k, _p(ids), _p(sc), _p(cnt)))
+        return ids, sc, cnt
+
+    def search_rerank(self, indptr, coords, vals, k: int, k_prime: int):
+        """Alg. 7 with k' = k_prime: (ids, exact scores, counts) from host buffers."""
+        ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        nq = len(ip) - 1
+        ids = np.zeros((nq, k), np.uint32)
+        sc = np.zeros((nq, k), np.float32)
+        cnt = np.zeros(nq, np.uint32)
+        self._check(lib().snn_search_rerank(self._h, nq, _p(ip), _p(c), _p(v), k, k_prime, _p(ids), _p(sc), _p(cnt)))
+        return ids, sc, cnt
+
+    def search_rerank_dev(self, indptr, coords, vals, k: int, k_prime: int, out=None, stream=None,
+                          total: Optional[int] = None):
+        """Alg. 7 with k' = k_prime on device tensors; outputs (ids, exact scores, counts)."""
+        nq = indptr.numel() - 1
+        if total is None:
+            total = int(coords.numel())
+        dev = indptr.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev),
+                   torch.empty(nq, dtype=torch.int32, device=dev))
+        ids, sc, cnt = out
+        assert indptr.dtype == torch.int64 and coords.dtype == torch.int32 and vals.dtype == torch.float32
+        assert indptr.is_contiguous() and coords.is_contiguous() and vals.is_contiguous()
+        assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
+        self._check(lib().snn_search_rerank_dev(self._h, nq, _tp(indptr), int(total), _tp(coords), _tp(vals), k,
+                                                k_prime, _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
         return ids, sc, cnt
 
     def search_batch_dev(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, out=None, stream=None,

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsnn.so")
-SOURCES = ["kernels_index.hip", "kernels_search.hip", "kernels_merge.hip", "kernels_mlp.hip", "snn_api.cpp",
+SOURCES = ["kernels_index.hip", "kernels_search.hip", "kernels_merge.hip", "kernels_mlp.hip", "kernels_rerank.hip", "snn_api.cpp",
            "snn_extras.cpp", "snn_tune.cpp", "snn_filter.cpp", "snn_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

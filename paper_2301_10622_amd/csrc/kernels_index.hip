@@ -12,7 +12,9 @@ namespace snn {
 //   2. the column `slot` of U and L is written whole (buckets no coordinate
 //      maps to get 0), so a reused column holds no trace of its last owner;
 //   3. the slot's bit is set in the posting bitmap of every coordinate, in the
-//      live bitmap, and slot2id records the external id.
+//      live bitmap, and slot2id records the external id;
+//   4. with a forward store, the document's (coordinate, value) pairs are
+//      copied to its region (doc_off, placed by the host).
 // The caller guarantees the slot's old postings were cleared before (delete).
 // ---------------------------------------------------------------------------
 constexpr int kInsertMaxM = 1024;
@@ -21,7 +23,8 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
                                                const uint32_t *__restrict__ ids,
                                                const uint64_t *__restrict__ indptr,
                                                const uint32_t *__restrict__ coords,
-                                               const float *__restrict__ vals) {
+                                               const float *__restrict__ vals,
+                                               const uint64_t *__restrict__ doc_off) {
   __shared__ uint32_t umax[kInsertMaxM];
   __shared__ uint32_t umin[kInsertMaxM];
   const uint32_t d = blockIdx.x;
@@ -55,6 +58,15 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
     ix.U[(size_t)b * ix.cap + slot] = a ? key_value(a) : 0.0f;
     ix.L[(size_t)b * ix.cap + slot] = (c != 0xFFFFFFFFu) ? key_value(c) : 0.0f;
   }
+  if (doc_off) {
+    const uint64_t o = doc_off[d];
+    for (uint64_t e = e0 + lane; e < e1; e += 64)
+      ix.fwd[o + (e - e0)] = make_uint2(coords[e], __builtin_bit_cast(uint32_t, vals[e]));
+    if (lane == 0) {
+      ix.fwd_off[slot] = o;
+      ix.fwd_len[slot] = (uint32_t)(e1 - e0);
+    }
+  }
   if (lane == 0) {
     ix.slot2id[slot] = ids[d];
     atomicOr((unsigned long long *)&ix.live[word], (unsigned long long)bit);
@@ -62,10 +74,12 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
 }
 
 hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
-                         const uint64_t *indptr, const uint32_t *coords, const float *vals, hipStream_t s) {
+                         const uint64_t *indptr, const uint32_t *coords, const float *vals, const uint64_t *doc_off,
+                         hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (ix.m > (uint32_t)kInsertMaxM) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_insert, dim3(n), dim3(64), 0, s, ix, n, slots, ids, indptr, coords, vals);
+  if ((doc_off != nullptr) != (ix.fwd != nullptr)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_insert, dim3(n), dim3(64), 0, s, ix, n, slots, ids, indptr, coords, vals, doc_off);
   return hipGetLastError();
 }
 

@@ -145,7 +145,7 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   if (!out) return SNN_E_INVALID;
   *out = nullptr;
   if (!cfg || cfg->dim == 0 || cfg->m == 0 || cfg->h == 0 || cfg->h > 4 || cfg->capacity == 0 ||
-      cfg->capacity > (1u << 31) || cfg->flags != 0 || cfg->dim >= (1u << 31))
+      cfg->capacity > (1u << 31) || (cfg->flags & ~SNN_FORWARD_STORE) != 0 || cfg->dim >= (1u << 31))
     return SNN_E_INVALID;
   snn_index *ix = new (std::nothrow) snn_index();
   if (!ix) return SNN_E_NOMEM;
@@ -193,6 +193,20 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   }
   ix->slot_id.assign(ix->cap, 0xFFFFFFFFu);
   ix->fwd.resize(ix->cap);
+  if (cfg->flags & SNN_FORWARD_STORE) {
+    ix->has_fwd = true;
+    ix->fwd_roff.assign(ix->cap, 0);
+    ix->fwd_rlog.assign(ix->cap, 0);
+    ix->fwd_free.resize(64);
+    if (hipMalloc(&d.fwd_off, (size_t)ix->cap * 8) != hipSuccess ||
+        hipMalloc(&d.fwd_len, (size_t)ix->cap * 4) != hipSuccess ||
+        launch_fill_u32(d.fwd_len, 0u, ix->cap, ix->stream) != hipSuccess ||
+        launch_fill_u32((uint32_t *)d.fwd_off, 0u, (size_t)ix->cap * 2, ix->stream) != hipSuccess ||
+        rerank_init() != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess) {
+      snn_destroy(ix);
+      return SNN_E_NOMEM;
+    }
+  }
   ix->tune_init();
   *out = ix;
   return SNN_OK;
@@ -210,6 +224,9 @@ extern "C" void snn_destroy(snn_index *ix) {
   if (d.L) (void)hipFree(d.L);
   if (d.slot2id) (void)hipFree(d.slot2id);
   if (d.bucket) (void)hipFree(d.bucket);
+  if (d.fwd) (void)hipFree(d.fwd);
+  if (d.fwd_off) (void)hipFree(d.fwd_off);
+  if (d.fwd_len) (void)hipFree(d.fwd_len);
   ix->up.release();
   ix->pin.release();
   ix->wsp.release();
@@ -226,13 +243,75 @@ extern "C" const char *snn_last_error(const snn_index *ix) {
 // ---------------------------------------------------------------------------
 // insert / delete
 // ---------------------------------------------------------------------------
+// Forward-store regions for n documents about to be written to `slots`
+// (document r has ptr[r + 1] - ptr[r] entries). A slot keeps its region while
+// the new document fits; otherwise the region goes to the free list of its
+// size class and the document gets one of size 2^ceil(log2(len)) (at least 16
+// entries), from that class's free list or from the top of the store. The
+// store grows (doubling, contents copied) before any placement changes, so a
+// failed allocation leaves the index as it was.
+snn_status snn_index::fwd_place(const uint32_t *slots, const uint64_t *ptr, size_t n, uint64_t *doc_off) {
+  auto lg_of = [](uint64_t len) {
+    uint32_t lg = 4;
+    while ((1ull << lg) < len) ++lg;
+    return lg;
+  };
+  uint64_t worst = fwd_top;
+  for (size_t r = 0; r < n; ++r) worst += 1ull << lg_of(ptr[r + 1] - ptr[r]);
+  if (worst > fwd_cap || !dev.fwd) {
+    const uint64_t want = std::max<uint64_t>(std::max<uint64_t>(worst, fwd_cap * 2), (uint64_t)1 << 20);
+    uint2 *p = nullptr;
+    HIP_TRY(this, hipMalloc(&p, want * 8), "forward store");
+    if (dev.fwd) {
+      hipError_t e = hipDeviceSynchronize();  // in-flight searches may still read the old store
+      if (e == hipSuccess && fwd_top) e = hipMemcpy(p, dev.fwd, fwd_top * 8, hipMemcpyDeviceToDevice);
+      if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "forward store growth");
+      }
+      (void)hipFree(dev.fwd);
+    }
+    dev.fwd = p;
+    fwd_cap = want;
+    graphs.clear();  // captured launches hold the old address
+  }
+  for (size_t r = 0; r < n; ++r) {
+    const uint64_t len = ptr[r + 1] - ptr[r];
+    const uint32_t s = slots[r];
+    if (fwd_rlog[s] && (1ull << fwd_rlog[s]) >= len) {
+      doc_off[r] = fwd_roff[s];
+      continue;
+    }
+    if (fwd_rlog[s]) fwd_free[fwd_rlog[s]].push_back(fwd_roff[s]);
+    const uint32_t lg = lg_of(len);
+    uint64_t off;
+    if (!fwd_free[lg].empty()) {
+      off = fwd_free[lg].back();
+      fwd_free[lg].pop_back();
+    } else {
+      off = fwd_top;
+      fwd_top += 1ull << lg;
+    }
+    fwd_roff[s] = off;
+    fwd_rlog[s] = lg;
+    doc_off[r] = off;
+  }
+  return SNN_OK;
+}
+
 snn_status snn_index::upload_and_insert(const std::vector<uint32_t> &slots, const std::vector<uint32_t> &ids,
                                         const std::vector<uint64_t> &indptr, const std::vector<uint32_t> &coords,
                                         const std::vector<float> &vals, size_t r0, size_t r1) {
   const size_t n = r1 - r0;
   const uint64_t e0 = indptr[r0], e1 = indptr[r1];
   const size_t ne = (size_t)(e1 - e0);
-  const size_t bytes = n * 4 * 2 + (n + 1) * 8 + ne * 8 + 64;
+  std::vector<uint64_t> doc_off;
+  if (has_fwd) {
+    doc_off.resize(n);
+    snn_status st = fwd_place(slots.data() + r0, indptr.data() + r0, n, doc_off.data());
+    if (st != SNN_OK) return st;
+  }
+  const size_t bytes = n * 4 * 2 + (n + 1) * 8 + ne * 8 + n * 8 + 64;
   HIP_TRY(this, pin.ensure(bytes, stream), "insert staging");
   HIP_TRY(this, up.ensure(bytes, stream), "insert upload");
   char *hp = (char *)pin.p;
@@ -243,11 +322,15 @@ snn_status snn_index::upload_and_insert(const std::vector<uint32_t> &slots, cons
   for (size_t r = 0; r <= n; ++r) ip[r] = indptr[r0 + r] - e0;
   memcpy(hp + o_c, coords.data() + e0, ne * 4);
   memcpy(hp + o_v, vals.data() + e0, ne * 4);
+  const size_t o_off = (o_v + ne * 4 + 7) / 8 * 8;
+  if (has_fwd) memcpy(hp + o_off, doc_off.data(), n * 8);
   char *dp = (char *)up.p;
-  HIP_TRY(this, hipMemcpyAsync(dp, hp, o_v + ne * 4, hipMemcpyHostToDevice, stream), "insert copy");
+  HIP_TRY(this, hipMemcpyAsync(dp, hp, has_fwd ? o_off + n * 8 : o_v + ne * 4, hipMemcpyHostToDevice, stream),
+          "insert copy");
   HIP_TRY(this,
           launch_insert(dev, (uint32_t)n, (uint32_t *)(dp + o_slots), (uint32_t *)(dp + o_ids),
-                        (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v), stream),
+                        (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v),
+                        has_fwd ? (uint64_t *)(dp + o_off) : nullptr, stream),
           "insert kernel");
   HIP_TRY(this, hipStreamSynchronize(stream), "insert sync");
   return SNN_OK;
@@ -375,8 +458,8 @@ extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete
 
 // Device workspace for one batch: prepared entries, per-query state, tile
 // candidates. Laid out in one allocation.
-snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, SearchWs &w,
-                                        Workspace &W, hipStream_t stream) {
+snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, bool slots,
+                                        SearchWs &w, Workspace &W, hipStream_t stream) {
   const uint32_t h = cfg.h;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t o = 0;
@@ -416,6 +499,19 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.stats = (unsigned long long *)(p + o_stats);
   w.cand = (uint64_t *)W.cand.p;
   w.cand2 = (uint64_t *)W.cand2.p;
+  w.cslot = w.cslot2 = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
+  w.rr_sc = nullptr;
+  if (slots) {
+    HIP_TRY(this, W.cslot.ensure((size_t)nq * tiles * k * 4 + 64, stream), "candidate slots");
+    HIP_TRY(this, W.cslot2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 4 + 64, stream), "candidate slots");
+    HIP_TRY(this, W.rr.ensure((size_t)nq * k * 12 + (size_t)nq * 4 + 1024, stream), "re-rank candidates");
+    w.cslot = (uint32_t *)W.cslot.p;
+    w.cslot2 = (uint32_t *)W.cslot2.p;
+    w.rr_ids = (uint32_t *)W.rr.p;
+    w.rr_sc = (float *)(w.rr_ids + (size_t)nq * k);
+    w.rr_slot = (uint32_t *)(w.rr_sc + (size_t)nq * k);
+    w.rr_cnt = w.rr_slot + (size_t)nq * k;
+  }
   return SNN_OK;
 }
 
@@ -434,9 +530,12 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
   const uint32_t *in_cnt = w.cand_cnt;
   uint64_t *bufs[2] = {w.cand2, w.cand};
   uint32_t *cnts[2] = {w.cand_cnt2, w.cand_cnt};
+  uint32_t *sbufs[2] = {w.cslot2, w.cslot};
+  const uint32_t *in_slot = j.slots ? w.cslot : nullptr;
   int lvl = 0;
   for (;;) {
     MergeArgs m{};
+    m.in_slot = in_slot;
     m.groups_in = G;
     m.fanin = std::min(F, G);
     m.groups_out = (G + m.fanin - 1) / m.fanin;
@@ -452,10 +551,12 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
     if (m.groups_out > 1) {
       m.out = bufs[lvl & 1];
       m.out_cnt = cnts[lvl & 1];
+      if (j.slots) m.out_slot = sbufs[lvl & 1];
     } else {
       m.res_ids = j.res_ids;
       m.res_scores = j.res_scores;
       m.res_cnt = j.res_cnt;
+      m.res_slots = j.res_slots;
       m.fallback = j.set_fallback ? w.fallback : nullptr;
     }
     for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
@@ -466,6 +567,7 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
     if (m.groups_out == 1) break;
     in = m.out;
     in_cnt = m.out_cnt;
+    in_slot = m.out_slot;
     G = m.groups_out;
     ++lvl;
   }
@@ -515,14 +617,18 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   a.vis = vis;
   a.dirty = dirty;
   a.nselect = w.stats + 2;
+  const bool rerank = o.rerank_k != 0;
+  a.cand_slot = rerank ? w.cslot : nullptr;
   MergeJob mj;
   mj.tiles = p.tiles;
   mj.k = p.k;
   mj.kq = o.kq;
   mj.keff = keff;
-  mj.res_ids = p.d_ids;
-  mj.res_scores = p.d_sc;
-  mj.res_cnt = p.d_cnt;
+  mj.res_ids = rerank ? w.rr_ids : p.d_ids;
+  mj.res_scores = rerank ? w.rr_sc : p.d_sc;
+  mj.res_cnt = rerank ? w.rr_cnt : p.d_cnt;
+  mj.res_slots = rerank ? w.rr_slot : nullptr;
+  mj.slots = rerank;
   mj.emitted = w.stats;
   mj.set_fallback = true;
   if (p.mode == SNN_MODE_PLAIN) {
@@ -565,7 +671,23 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   mj.q0 = 0;
   mj.nqm = p.nq;
   st = enqueue_merge(w, mj, s);
-  if (st != SNN_OK || !lp) return st;
+  if (st != SNN_OK) return st;
+  if (rerank) {
+    RerankArgs r{};
+    r.ix = dev;
+    r.qd = qd;
+    r.kprime = p.k;
+    r.k = o.rerank_k;
+    r.hash_cap = o.hash_cap;
+    r.cand_ids = w.rr_ids;
+    r.cand_slots = w.rr_slot;
+    r.cand_cnt = w.rr_cnt;
+    r.out_ids = p.d_ids;
+    r.out_scores = p.d_sc;
+    r.out_cnt = p.d_cnt;
+    HIP_TRY(this, launch_rerank(r, p.nq, s), "re-rank kernel");
+  }
+  if (!lp) return SNN_OK;
   // plain fallback of the learned filter, over the flagged queries only
   HIP_TRY(this, launch_fallback_list(p.nq, w.fallback, w.qlist, w.nlist, w.thr, s), "fallback list");
   a.qlist = w.qlist;
@@ -600,7 +722,7 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   const uint32_t tile_docs = (uint32_t)kBlock * p.R;
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
-  return prepare_workspace(nq, total - o.ebase, k, p.tiles, p.w, o.wsp ? *o.wsp : wsp, s);
+  return prepare_workspace(nq, total - o.ebase, k, p.tiles, o.rerank_k != 0, p.w, o.wsp ? *o.wsp : wsp, s);
 }
 
 snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
@@ -638,6 +760,11 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
   Workspace &W = o.wsp ? *o.wsp : wsp;
   key.ws = W.ws.p; key.cand = W.cand.p; key.cand2 = W.cand2.p; key.qseq = o.qseq; key.ebase = o.ebase;
+  key.rerank_k = o.rerank_k;
+  key.hash_cap = o.hash_cap;
+  key.cslot = W.cslot.p;
+  key.rr = W.rr.p;
+  key.fwd = dev.fwd;
   if (const LearnedPass *lp = o.learned) {
     key.lX = lp->X; key.ly = lp->yhat; key.lthr = lp->thr; key.lkeff = lp->keff; key.lPb = lp->Pb;
     key.ltab = lp->table; key.lkeff_v = lp->keff_value;
@@ -669,19 +796,30 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   return SNN_OK;
 }
 
-extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
-                                       const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
-                                       uint32_t *out_counts) {
-  if (!ix) return SNN_E_INVALID;
-  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
+// LDS hash slots the re-rank kernel needs for queries of at most `max_nnz`
+// entries: a power of two at least twice that (a table at most half full).
+static uint32_t rerank_hash_cap(uint64_t max_nnz) {
+  uint64_t ub = std::min<uint64_t>(max_nnz, (uint64_t)kPrepCap);
+  uint32_t cap = 64;
+  while (cap < 2 * ub) cap <<= 1;
+  return cap;
+}
+
+// Host-buffer batch search: validate, stage, search (re-ranked when kprime > 0:
+// k' = kprime candidates, k returned), read back.
+static snn_status search_host(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                              const float *vals, uint32_t k, uint32_t kprime, uint32_t *out_ids, float *out_scores,
+                              uint32_t *out_counts) {
   if (nq == 0) return SNN_OK;
   if (!indptr || !out_ids || !out_scores || !out_counts) return ix->fail(SNN_E_INVALID, "search: null pointer");
   std::vector<uint32_t> oc, scratch;
   std::vector<float> ov;
+  uint64_t max_len = 0;
   for (uint32_t r = 0; r < nq; ++r) {
     if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "search: indptr not monotone");
     uint64_t len = indptr[r + 1] - indptr[r];
     if (len > (uint64_t)kPrepCap) return ix->fail(SNN_E_INVALID, "search: a query has more than %d entries", kPrepCap);
+    max_len = std::max(max_len, len);
     oc.clear();
     ov.clear();
     if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "search"))
@@ -707,8 +845,13 @@ extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_
   uint32_t *d_ids = (uint32_t *)(dp + o_out);
   float *d_sc = (float *)(d_ids + (size_t)nq * k);
   uint32_t *d_cnt = (uint32_t *)(d_sc + (size_t)nq * k);
-  snn_status st = ix->run_search(nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v), k,
-                                 SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, SearchOpts{});
+  SearchOpts o;
+  if (kprime) {
+    o.rerank_k = k;
+    o.hash_cap = rerank_hash_cap(max_len);
+  }
+  snn_status st = ix->run_search(nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v),
+                                 kprime ? kprime : k, SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, o);
   if (st != SNN_OK) return st;
   HIP_TRY(ix, hipMemcpyAsync(hp + o_out, d_ids, out_bytes - 64, hipMemcpyDeviceToHost, s), "search readback");
   HIP_TRY(ix, hipStreamSynchronize(s), "search sync");
@@ -719,6 +862,49 @@ extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_
   memcpy(out_scores, h_sc, (size_t)nq * k * 4);
   memcpy(out_counts, h_cnt, (size_t)nq * 4);
   return SNN_OK;
+}
+
+extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                       const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
+                                       uint32_t *out_counts) {
+  if (!ix) return SNN_E_INVALID;
+  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
+  return search_host(ix, nq, indptr, coords, vals, k, 0, out_ids, out_scores, out_counts);
+}
+
+static snn_status check_rerank(snn_index *ix, uint32_t k, uint32_t k_prime) {
+  if (!ix->has_fwd) return ix->fail(SNN_E_INVALID, "re-rank: the index has no forward store (SNN_FORWARD_STORE)");
+  if (k == 0 || k_prime < k || k_prime > kMaxK)
+    return ix->fail(SNN_E_INVALID, "re-rank: need 1 <= k <= k' <= %u (k = %u, k' = %u)", kMaxK, k, k_prime);
+  return SNN_OK;
+}
+
+extern "C" snn_status snn_search_rerank(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                        const float *vals, uint32_t k, uint32_t k_prime, uint32_t *out_ids,
+                                        float *out_scores, uint32_t *out_counts) {
+  if (!ix) return SNN_E_INVALID;
+  snn_status st = check_rerank(ix, k, k_prime);
+  if (st != SNN_OK) return st;
+  return search_host(ix, nq, indptr, coords, vals, k, k_prime, out_ids, out_scores, out_counts);
+}
+
+extern "C" snn_status snn_search_rerank_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                            const uint32_t *coords, const float *vals, uint32_t k, uint32_t k_prime,
+                                            uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream) {
+  if (!ix) return SNN_E_INVALID;
+  snn_status st = check_rerank(ix, k, k_prime);
+  if (st != SNN_OK) return st;
+  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
+  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
+    return ix->fail(SNN_E_INVALID, "search: null pointer");
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  ix->last_nq = nq;
+  ix->last_mode = SNN_MODE_BATCHED;
+  SearchOpts o;
+  o.rerank_k = k;
+  o.hash_cap = rerank_hash_cap(total);  // no query holds more entries than the batch
+  return ix->run_search(nq, indptr, total, coords, vals, k_prime, SNN_MODE_BATCHED, out_ids, out_scores, out_counts,
+                        s, o);
 }
 
 extern "C" snn_status snn_search(snn_index *ix, uint32_t nnz, const uint32_t *coords, const float *vals, uint32_t k,

@@ -31,10 +31,14 @@ struct PinBuf {
 // Device buffers of one in-flight search batch.
 struct Workspace {
   DevBuf ws, cand, cand2;
+  DevBuf cslot, cslot2, rr;  // re-rank: candidate slots per level, the merged k' candidates
   void release() {
     ws.release();
     cand.release();
     cand2.release();
+    cslot.release();
+    cslot2.release();
+    rr.release();
   }
 };
 
@@ -45,6 +49,9 @@ struct SearchWs {
   uint32_t *cand_cnt = nullptr, *cand_cnt2 = nullptr, *queue = nullptr;
   uint64_t *cand = nullptr, *cand2 = nullptr;
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
+  uint32_t *cslot = nullptr, *cslot2 = nullptr;  // re-rank: slot of each candidate, per merge level
+  uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' merged candidates
+  float *rr_sc = nullptr;
   unsigned long long *stats = nullptr;          // candidates emitted, selecting tiles (main, fallback pass)
 };
 
@@ -72,6 +79,8 @@ struct LearnedPass {
 // Optional per-query inputs of a search (device arrays of nq entries).
 struct SearchOpts {
   const LearnedPass *learned = nullptr;  // filtered pass with a device-side plain fallback
+  uint32_t rerank_k = 0;                 // > 0: the batch k is k' of Alg. 7 and this many are returned
+  uint32_t hash_cap = 0;                 // re-rank: LDS hash slots per query
   const uint32_t *thr_init = nullptr;  // initial inclusive threshold keys (learned filter)
   const uint32_t *kq = nullptr;        // per-query k (<= the batch k)
   const uint32_t *keff = nullptr;      // count below which the filter check reports a fallback
@@ -87,6 +96,7 @@ struct MergeJob {
   uint32_t q0 = 0, nqm = 0, tiles = 0, k = 0;
   const uint32_t *kq = nullptr, *keff = nullptr;
   uint32_t *res_ids = nullptr, *res_cnt = nullptr, *res_slots = nullptr;
+  bool slots = false;  // carry the candidates' slots (cslot / cslot2) through the levels
   float *res_scores = nullptr;
   const uint32_t *qlist = nullptr, *nlist = nullptr;
   unsigned long long *emitted = nullptr;
@@ -112,13 +122,15 @@ struct GraphKey {
   bool persistent, prof;
   const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2, *qseq;
   const void *lX, *ly, *lthr, *lkeff, *lPb, *ltab;
-  uint32_t ldelta, lkeff_v;
+  uint32_t ldelta, lkeff_v, rerank_k, hash_cap;
+  const void *cslot, *rr, *fwd;
   uint64_t ebase;
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
            lX == o.lX && ly == o.ly && lthr == o.lthr && lkeff == o.lkeff && lPb == o.lPb && ltab == o.ltab &&
-           ldelta == o.ldelta && lkeff_v == o.lkeff_v &&
+           ldelta == o.ldelta && lkeff_v == o.lkeff_v && rerank_k == o.rerank_k && hash_cap == o.hash_cap &&
+           cslot == o.cslot && rr == o.rr && fwd == o.fwd &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
            ws == o.ws && cand == o.cand && cand2 == o.cand2 && qseq == o.qseq && ebase == o.ebase &&
@@ -179,6 +191,15 @@ struct snn_index {
   std::vector<uint32_t> slot_id;             // external id per slot (0xFFFFFFFF = free)
   std::vector<std::vector<uint32_t>> fwd;    // coordinates of the document in each slot
   std::vector<uint32_t> free_slots;          // freed columns, reused first
+  // forward store (SNN_FORWARD_STORE): device entries dev.fwd[0 .. fwd_cap), of
+  // which [0, fwd_top) have been handed out. Each slot owns a region of a
+  // power-of-two size; a region too small for a new document goes to the free
+  // list of its size class.
+  bool has_fwd = false;
+  uint64_t fwd_top = 0, fwd_cap = 0;
+  std::vector<uint64_t> fwd_roff;
+  std::vector<uint32_t> fwd_rlog;                    // log2 region size per slot (0: none)
+  std::vector<std::vector<uint64_t>> fwd_free;       // by log2 size
   uint32_t next_fresh = 0;                   // slots [0, next_fresh) have been used
   size_t live = 0;
   uint64_t mutations = 0;
@@ -215,13 +236,14 @@ struct snn_index {
   snn_status fail(snn_status st, const char *fmt, ...);
   snn_status hip_fail(hipError_t e, const char *what);
 
+  snn_status fwd_place(const uint32_t *slots, const uint64_t *ptr, size_t n, uint64_t *doc_off);
   snn_status upload_and_insert(const std::vector<uint32_t> &slots, const std::vector<uint32_t> &ids,
                                const std::vector<uint64_t> &indptr, const std::vector<uint32_t> &coords,
                                const std::vector<float> &vals, size_t r0, size_t r1);
   snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
-  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, snn::SearchWs &w,
-                               snn::Workspace &W, hipStream_t s);
+  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, bool slots,
+                               snn::SearchWs &w, snn::Workspace &W, hipStream_t s);
   uint32_t merge_fanin(uint32_t k) const;
   snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,

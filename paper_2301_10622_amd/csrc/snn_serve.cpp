@@ -230,20 +230,28 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
   auto flush_inserts = [&](uint32_t first_ins) -> snn_status {
     const uint32_t cnt = (uint32_t)g_slots.size();
     if (!cnt) return SNN_OK;
-    uint32_t *hp = (uint32_t *)arena.take(ix, (size_t)cnt * 12, M);
+    // slots, ids, sequence numbers, then (forward store) each document's region
+    const size_t o_off = ((size_t)cnt * 12 + 7) / 8 * 8;
+    const size_t bytes = ix->has_fwd ? o_off + (size_t)cnt * 8 : (size_t)cnt * 12;
+    std::vector<uint64_t> doc_off;
+    if (ix->has_fwd) {
+      doc_off.resize(cnt);
+      snn_status fs = ix->fwd_place(g_slots.data(), hi_ptr.data() + first_ins, cnt, doc_off.data());
+      if (fs != SNN_OK) return fs;
+    }
+    uint32_t *hp = (uint32_t *)arena.take(ix, bytes, M);
     if (!hp) return ix->fail(SNN_E_NOMEM, "serve staging");
     memcpy(hp, g_slots.data(), cnt * 4);
     memcpy(hp + cnt, g_ids.data(), cnt * 4);
     memcpy(hp + 2 * cnt, g_seqs.data(), cnt * 4);
-    DevBuf &d = ix->up;
-    (void)d;
+    if (ix->has_fwd) memcpy((char *)hp + o_off, doc_off.data(), (size_t)cnt * 8);
     uint32_t *dp = nullptr;
-    HIP_TRY(ix, hipMallocAsync((void **)&dp, (size_t)cnt * 12, M), "serve upload");
-    HIP_TRY(ix, hipMemcpyAsync(dp, hp, (size_t)cnt * 12, hipMemcpyHostToDevice, M), "serve upload");
+    HIP_TRY(ix, hipMallocAsync((void **)&dp, bytes, M), "serve upload");
+    HIP_TRY(ix, hipMemcpyAsync(dp, hp, bytes, hipMemcpyHostToDevice, M), "serve upload");
     HIP_TRY(ix, launch_serve_mark(ix->vis, ix->dirty, cnt, dp, dp + 2 * cnt, 1, M), "serve mark");
     HIP_TRY(ix,
             launch_insert(ix->dev, cnt, dp, dp + cnt, (const uint64_t *)i_ptr.p + first_ins, (const uint32_t *)i_c.p,
-                          (const float *)i_v.p, M),
+                          (const float *)i_v.p, ix->has_fwd ? (const uint64_t *)((char *)dp + o_off) : nullptr, M),
             "serve insert");
     HIP_TRY(ix, hipFreeAsync(dp, M), "serve upload");
     g_slots.clear();

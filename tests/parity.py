@@ -80,3 +80,47 @@ def check_batch(gpu_ids, gpu_scores, gpu_counts, oracle_index, queries, k, live=
         c = int(gpu_counts[qi])
         check_query(gpu_ids[qi][:c], gpu_scores[qi][:c], s, a, pos_of_id, ids_of_pos, k, live, rel,
                     "%s q%d" % (what, qi))
+
+
+def check_rerank_query(gpu_ids, gpu_scores, est, est_abs, exact, exact_abs, ids_of_pos, k, kp, rel=REL, what=""):
+    """Alg. 7 result of one query against the oracle's FP64 estimates and exact
+    scores of every document. The k' candidates are fixed when no document
+    outside the oracle's top-k' lies within tolerance of its k'-th estimate
+    (twice the score tolerance, since both sides may round); then the GPU's k
+    results must be the oracle's top-k by exact score over those candidates, by
+    the rule of check_query. Otherwise the candidate set is open at its edge and
+    only what still holds is checked: every result is a candidate of some
+    valid top-k', its exact score is right and the list is sorted. Documents
+    that share no coordinate with the query score exactly 0 on both sides and
+    are ordered by id alike, so they never open the edge. Returns True when
+    the query was checked in full."""
+    gpu_ids = np.asarray(gpu_ids, dtype=np.int64)
+    order = np.lexsort((ids_of_pos, -est))
+    V = order[:kp]
+    assert len(gpu_ids) == min(k, len(V)), "%s count %d vs %d" % (what, len(gpu_ids), min(k, len(V)))
+    if len(V) == 0:
+        return True
+    skp, akp = est[V[-1]], est_abs[V[-1]]
+    near = np.abs(est - skp) <= 2 * rel * np.maximum(est_abs, akp) + 1e-30
+    if akp == 0:
+        # documents no query coordinate touches score exactly 0 on both sides;
+        # among them the lower id wins everywhere, so they fix the set
+        near &= est_abs > 0
+    outside = np.ones(len(est), bool)
+    outside[V] = False
+    open_edge = bool(np.any(near & outside))
+    if not open_edge:
+        ids_V = ids_of_pos[V]
+        pos_V = {int(i): p for p, i in enumerate(ids_V)}
+        check_query(gpu_ids, gpu_scores, exact[V], exact_abs[V], pos_V, ids_V, k, rel=rel, what=what)
+        return True
+    pos_of_id = {int(i): p for p, i in enumerate(ids_of_pos)}
+    allowed = set(V.tolist()) | set(np.nonzero(near)[0].tolist())
+    gpos = np.array([pos_of_id[int(i)] for i in gpu_ids], dtype=np.int64)
+    assert all(int(p) in allowed for p in gpos), "%s result outside every valid candidate set" % what
+    err = np.abs(np.asarray(gpu_scores, np.float64) - exact[gpos])
+    assert np.all(err <= rel * exact_abs[gpos] + 1e-30), "%s exact score mismatch" % what
+    for r in range(len(gpu_ids) - 1):
+        a, b = gpu_scores[r], gpu_scores[r + 1]
+        assert a > b or (a == b and gpu_ids[r] < gpu_ids[r + 1]), "%s order broken at rank %d" % (what, r)
+    return False
