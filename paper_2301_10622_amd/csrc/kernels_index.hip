@@ -23,7 +23,7 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
                                                const uint32_t *__restrict__ ids,
                                                const uint64_t *__restrict__ indptr,
                                                const uint32_t *__restrict__ coords,
-                                               const float *__restrict__ vals,
+                                               const float *__restrict__ vals, DevForward fw,
                                                const uint64_t *__restrict__ doc_off) {
   __shared__ uint32_t umax[kInsertMaxM];
   __shared__ uint32_t umin[kInsertMaxM];
@@ -61,10 +61,10 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
   if (doc_off) {
     const uint64_t o = doc_off[d];
     for (uint64_t e = e0 + lane; e < e1; e += 64)
-      ix.fwd[o + (e - e0)] = make_uint2(coords[e], __builtin_bit_cast(uint32_t, vals[e]));
+      fw.ent[o + (e - e0)] = make_uint2(coords[e], __builtin_bit_cast(uint32_t, vals[e]));
     if (lane == 0) {
-      ix.fwd_off[slot] = o;
-      ix.fwd_len[slot] = (uint32_t)(e1 - e0);
+      fw.off[slot] = o;
+      fw.len[slot] = (uint32_t)(e1 - e0);
     }
   }
   if (lane == 0) {
@@ -74,12 +74,12 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
 }
 
 hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
-                         const uint64_t *indptr, const uint32_t *coords, const float *vals, const uint64_t *doc_off,
-                         hipStream_t s) {
+                         const uint64_t *indptr, const uint32_t *coords, const float *vals, const DevForward &fw,
+                         const uint64_t *doc_off, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (ix.m > (uint32_t)kInsertMaxM) return hipErrorInvalidValue;
-  if ((doc_off != nullptr) != (ix.fwd != nullptr)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_insert, dim3(n), dim3(64), 0, s, ix, n, slots, ids, indptr, coords, vals, doc_off);
+  if ((doc_off != nullptr) != (fw.ent != nullptr)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_insert, dim3(n), dim3(64), 0, s, ix, n, slots, ids, indptr, coords, vals, fw, doc_off);
   return hipGetLastError();
 }
 

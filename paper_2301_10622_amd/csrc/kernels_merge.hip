@@ -150,6 +150,170 @@ hipError_t launch_merge(const MergeArgs &a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// Select: the final top-k of one query straight from all of its tile groups,
+// for large k where sorting every candidate would dominate. One workgroup per
+// query finds the k-th largest 64-bit key by most-significant-digit radix
+// select: each pass builds a 4,096-bin histogram (12-bit digits) of the keys
+// that share the prefix found so far and picks the bin holding the k-th key;
+// it stops once a bin holds exactly the keys still needed (normally after the
+// three passes that fix the 32-bit score; ties at the k-th score go on into
+// the id bits). The keys at or above the found prefix are then exactly the k
+// best; only they are sorted (bitonic, at most 4,096 in LDS).
+// ---------------------------------------------------------------------------
+constexpr int kSelBlock = 512;
+constexpr int kSelWaves = kSelBlock / 64;
+constexpr int kSelBins = 4096;
+
+template <bool kPay>
+__global__ __launch_bounds__(kSelBlock) void k_select(MergeArgs a) {
+  __shared__ uint32_t hist[kSelBins];
+  __shared__ uint32_t part[kSelBlock];
+  __shared__ uint64_t sel[kMaxK];
+  __shared__ uint32_t sels[kPay ? kMaxK : 1];
+  __shared__ uint32_t sh_bin, sh_need, sh_pos;
+  uint32_t q = a.q0 + blockIdx.y;
+  if (a.qlist) {
+    if (q >= *as_const(a.nlist)) return;
+    q = as_const(a.qlist)[q];
+  }
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t G = a.groups_in;
+  const uint32_t *cnts = a.in_cnt + (size_t)q * G;
+  const uint64_t *base = a.in + (size_t)q * G * a.kmax;
+  const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
+  const bool bad = a.status && a.status[q] != 0u;
+  // every key of the query: wave w walks groups w, w + 8, ..., its lanes the group's keys
+  auto for_each = [&](auto f) {
+    for (uint32_t g = (uint32_t)wave; g < G; g += kSelWaves) {
+      const uint32_t c = cnts[g];
+      const uint64_t *src = base + (size_t)g * a.kmax;
+      for (uint32_t e = (uint32_t)lane; e < c; e += 64) f(src[e], g, e);
+    }
+  };
+  // M = number of candidates
+  uint32_t mine = 0;
+  for (uint32_t g = (uint32_t)tid; g < G; g += kSelBlock) mine += cnts[g];
+  part[tid] = mine;
+  __syncthreads();
+  for (int d = kSelBlock / 2; d > 0; d >>= 1) {
+    if (tid < d) part[tid] += part[tid + d];
+    __syncthreads();
+  }
+  const uint32_t M = part[0];
+  __syncthreads();
+  if (a.emitted && tid == 0 && M) atomicAdd(a.emitted, (unsigned long long)M);
+  const uint32_t keep = bad ? 0u : min(M, kq);
+  uint64_t T = 0;  // the result is every key >= T
+  if (keep > 0 && keep < M) {
+    uint64_t P = 0;
+    int pb = 0;
+    uint32_t need = keep;
+    for (;;) {
+      const int d = min(12, 64 - pb);
+      const uint32_t nb = 1u << d;
+      for (uint32_t i = tid; i < nb; i += kSelBlock) hist[i] = 0u;
+      __syncthreads();
+      for_each([&](uint64_t key, uint32_t, uint32_t) {
+        if (pb == 0 || (key >> (64 - pb)) == P)
+          atomicAdd(&hist[(uint32_t)(key >> (64 - pb - d)) & (nb - 1u)], 1u);
+      });
+      __syncthreads();
+      // counts above each thread's 8 bins (suffix scan), then the bin that
+      // holds the need-th largest key
+      const uint32_t per = (nb + kSelBlock - 1) / kSelBlock;
+      const uint32_t b0 = (uint32_t)tid * per;
+      uint32_t s = 0;
+      for (uint32_t b = b0; b < b0 + per && b < nb; ++b) s += hist[b];
+      part[tid] = s;
+      __syncthreads();
+      for (int off = 1; off < kSelBlock; off <<= 1) {
+        const uint32_t v = tid + off < kSelBlock ? part[tid + off] : 0u;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+      }
+      uint32_t above = part[tid] - s;
+      for (int b = (int)min(b0 + per, nb) - 1; b >= (int)b0; --b) {
+        const uint32_t h = hist[b];
+        if (above < need && above + h >= need) {
+          sh_bin = (uint32_t)b;
+          sh_need = need - above;
+        }
+        above += h;
+      }
+      __syncthreads();
+      const uint32_t bin = sh_bin;
+      const uint32_t in_bin = hist[bin];
+      need = sh_need;
+      P = (P << d) | bin;
+      pb += d;
+      __syncthreads();
+      if (in_bin == need || pb == 64) {
+        T = pb == 64 ? P : (P << (64 - pb));
+        break;
+      }
+    }
+  }
+  // the keep best keys (with their slots), then sorted
+  if (tid == 0) sh_pos = 0;
+  __syncthreads();
+  if (keep > 0) {
+    for_each([&](uint64_t key, uint32_t g, uint32_t e) {
+      if (key >= T) {
+        const uint32_t pos = atomicAdd(&sh_pos, 1u);
+        sel[pos] = key;
+        if (kPay) sels[pos] = a.in_slot[((size_t)q * G + g) * a.kmax + e];
+      }
+    });
+  }
+  __syncthreads();
+  uint32_t np = 1;
+  while (np < keep) np <<= 1;
+  for (uint32_t i = keep + tid; i < np; i += kSelBlock) sel[i] = 0ull;
+  for (uint32_t size = 2; size <= np; size <<= 1)
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (uint32_t i = tid; i < (np >> 1); i += kSelBlock) {
+        const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
+        const uint32_t hi = lo + stride;
+        const bool down = (lo & size) == 0;
+        const uint64_t x = sel[lo], y = sel[hi];
+        if ((x < y) == down) {
+          sel[lo] = y;
+          sel[hi] = x;
+          if (kPay) {
+            const uint32_t t = sels[lo];
+            sels[lo] = sels[hi];
+            sels[hi] = t;
+          }
+        }
+      }
+    }
+  __syncthreads();
+  uint32_t *ids = a.res_ids + (size_t)q * a.kmax;
+  float *sc = a.res_scores + (size_t)q * a.kmax;
+  for (uint32_t r = tid; r < keep; r += kSelBlock) {
+    const uint64_t key = sel[r];
+    ids[r] = 0xFFFFFFFFu - (uint32_t)key;
+    sc[r] = key_value((uint32_t)(key >> 32));
+    if (kPay) a.res_slots[(size_t)q * a.kmax + r] = sels[r];
+  }
+  if (tid == 0) {
+    a.res_cnt[q] = keep;
+    if (a.fallback) a.fallback[q] = (!bad && a.keff && M < a.keff[q]) ? 1u : 0u;
+  }
+}
+
+hipError_t launch_select(const MergeArgs &a, hipStream_t s) {
+  if (a.kmax > kMaxK || a.groups_out != 1 || !a.res_ids || !a.res_scores || !a.res_cnt) return hipErrorInvalidValue;
+  const bool pay = a.in_slot != nullptr;
+  if (pay && a.res_slots == nullptr) return hipErrorInvalidValue;
+  if (pay) hipLaunchKernelGGL(k_select<true>, dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else hipLaunchKernelGGL(k_select<false>, dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Fallback list of the learned filter: one workgroup compacts the queries whose
 // filtered merge kept fewer than the required candidates, in query order, into
 // qlist[0 .. *nlist), and clears their shared thresholds for the plain pass.

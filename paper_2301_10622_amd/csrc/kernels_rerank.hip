@@ -85,8 +85,8 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
     if (c < n) {
       const uint32_t slot = a.cand_slots[cbase + c];
       id = a.cand_ids[cbase + c];
-      off = a.ix.fwd_off[slot];
-      len = a.ix.fwd_len[slot];
+      off = a.fw.off[slot];
+      len = a.fw.len[slot];
     }
     const uint32_t here = min(64u, n - base);
     for (uint32_t t = 0; t < here; ++t) {
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
       const uint32_t ln = shfl_u32(len, (int)t);
       float acc = 0.0f;
       for (uint32_t e = (uint32_t)lane; e < ln; e += 64u) {
-        const uint2 en = a.ix.fwd[o + e];
+        const uint2 en = a.fw.ent[o + e];
         acc = __builtin_fmaf(lookup(en.x), __builtin_bit_cast(float, en.y), acc);
       }
 #pragma unroll
@@ -149,7 +149,7 @@ hipError_t rerank_init() {
 hipError_t launch_rerank(const RerankArgs &a, uint32_t nq, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   if (a.kprime == 0 || a.kprime > kMaxK || a.k == 0 || a.k > a.kprime || a.hash_cap < 64 || a.hash_cap > 8192 ||
-      (a.hash_cap & (a.hash_cap - 1)) || !a.ix.fwd)
+      (a.hash_cap & (a.hash_cap - 1)) || !a.fw.ent)
     return hipErrorInvalidValue;
   const size_t lds = rerank_lds(a);
   for (uint32_t c0 = 0; c0 < nq; c0 += 65535u) {

@@ -198,10 +198,10 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
     ix->fwd_roff.assign(ix->cap, 0);
     ix->fwd_rlog.assign(ix->cap, 0);
     ix->fwd_free.resize(64);
-    if (hipMalloc(&d.fwd_off, (size_t)ix->cap * 8) != hipSuccess ||
-        hipMalloc(&d.fwd_len, (size_t)ix->cap * 4) != hipSuccess ||
-        launch_fill_u32(d.fwd_len, 0u, ix->cap, ix->stream) != hipSuccess ||
-        launch_fill_u32((uint32_t *)d.fwd_off, 0u, (size_t)ix->cap * 2, ix->stream) != hipSuccess ||
+    if (hipMalloc(&ix->fw.off, (size_t)ix->cap * 8) != hipSuccess ||
+        hipMalloc(&ix->fw.len, (size_t)ix->cap * 4) != hipSuccess ||
+        launch_fill_u32(ix->fw.len, 0u, ix->cap, ix->stream) != hipSuccess ||
+        launch_fill_u32((uint32_t *)ix->fw.off, 0u, (size_t)ix->cap * 2, ix->stream) != hipSuccess ||
         rerank_init() != hipSuccess || hipStreamSynchronize(ix->stream) != hipSuccess) {
       snn_destroy(ix);
       return SNN_E_NOMEM;
@@ -224,9 +224,9 @@ extern "C" void snn_destroy(snn_index *ix) {
   if (d.L) (void)hipFree(d.L);
   if (d.slot2id) (void)hipFree(d.slot2id);
   if (d.bucket) (void)hipFree(d.bucket);
-  if (d.fwd) (void)hipFree(d.fwd);
-  if (d.fwd_off) (void)hipFree(d.fwd_off);
-  if (d.fwd_len) (void)hipFree(d.fwd_len);
+  if (ix->fw.ent) (void)hipFree(ix->fw.ent);
+  if (ix->fw.off) (void)hipFree(ix->fw.off);
+  if (ix->fw.len) (void)hipFree(ix->fw.len);
   ix->up.release();
   ix->pin.release();
   ix->wsp.release();
@@ -258,20 +258,20 @@ snn_status snn_index::fwd_place(const uint32_t *slots, const uint64_t *ptr, size
   };
   uint64_t worst = fwd_top;
   for (size_t r = 0; r < n; ++r) worst += 1ull << lg_of(ptr[r + 1] - ptr[r]);
-  if (worst > fwd_cap || !dev.fwd) {
+  if (worst > fwd_cap || !fw.ent) {
     const uint64_t want = std::max<uint64_t>(std::max<uint64_t>(worst, fwd_cap * 2), (uint64_t)1 << 20);
     uint2 *p = nullptr;
     HIP_TRY(this, hipMalloc(&p, want * 8), "forward store");
-    if (dev.fwd) {
+    if (fw.ent) {
       hipError_t e = hipDeviceSynchronize();  // in-flight searches may still read the old store
-      if (e == hipSuccess && fwd_top) e = hipMemcpy(p, dev.fwd, fwd_top * 8, hipMemcpyDeviceToDevice);
+      if (e == hipSuccess && fwd_top) e = hipMemcpy(p, fw.ent, fwd_top * 8, hipMemcpyDeviceToDevice);
       if (e != hipSuccess) {
         (void)hipFree(p);
         return hip_fail(e, "forward store growth");
       }
-      (void)hipFree(dev.fwd);
+      (void)hipFree(fw.ent);
     }
-    dev.fwd = p;
+    fw.ent = p;
     fwd_cap = want;
     graphs.clear();  // captured launches hold the old address
   }
@@ -329,7 +329,7 @@ snn_status snn_index::upload_and_insert(const std::vector<uint32_t> &slots, cons
           "insert copy");
   HIP_TRY(this,
           launch_insert(dev, (uint32_t)n, (uint32_t *)(dp + o_slots), (uint32_t *)(dp + o_ids),
-                        (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v),
+                        (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v), fw,
                         has_fwd ? (uint64_t *)(dp + o_off) : nullptr, stream),
           "insert kernel");
   HIP_TRY(this, hipStreamSynchronize(stream), "insert sync");
@@ -524,6 +524,34 @@ uint32_t snn_index::merge_fanin(uint32_t k) const {
 
 // Enqueue the merge levels of one merge job.
 snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStream_t s) {
+  if (j.k >= kSelectMinK) {
+    // large k: one radix-select pass over every tile group of each query
+    MergeArgs m{};
+    m.groups_in = j.tiles;
+    m.fanin = j.tiles;
+    m.groups_out = 1;
+    m.kmax = j.k;
+    m.kq = j.kq;
+    m.keff = j.keff;
+    m.in = w.cand;
+    m.in_cnt = w.cand_cnt;
+    m.status = w.status;
+    m.qlist = j.qlist;
+    m.nlist = j.nlist;
+    m.emitted = j.emitted;
+    m.in_slot = j.slots ? w.cslot : nullptr;
+    m.res_ids = j.res_ids;
+    m.res_scores = j.res_scores;
+    m.res_cnt = j.res_cnt;
+    m.res_slots = j.res_slots;
+    m.fallback = j.set_fallback ? w.fallback : nullptr;
+    for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
+      m.q0 = j.q0 + c0;
+      m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
+      HIP_TRY(this, launch_select(m, s), "select kernel");
+    }
+    return SNN_OK;
+  }
   const uint32_t F = merge_fanin(j.k);
   uint32_t G = j.tiles;
   const uint64_t *in = w.cand;
@@ -674,7 +702,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   if (st != SNN_OK) return st;
   if (rerank) {
     RerankArgs r{};
-    r.ix = dev;
+    r.fw = fw;
     r.qd = qd;
     r.kprime = p.k;
     r.k = o.rerank_k;
@@ -764,7 +792,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.hash_cap = o.hash_cap;
   key.cslot = W.cslot.p;
   key.rr = W.rr.p;
-  key.fwd = dev.fwd;
+  key.fwd = fw.ent;
   if (const LearnedPass *lp = o.learned) {
     key.lX = lp->X; key.ly = lp->yhat; key.lthr = lp->thr; key.lkeff = lp->keff; key.lPb = lp->Pb;
     key.ltab = lp->table; key.lkeff_v = lp->keff_value;

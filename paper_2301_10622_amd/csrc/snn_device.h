@@ -10,10 +10,10 @@
 //                                 bucket (the transposed layout of Section 4.1)
 //   slot2id  uint32 [cap]         external id of the document in each slot
 //   bucket   uint32 [h][dim]      the random mappings pi_o(j)
-//   fwd      uint2  [entries]     forward store (optional): (coordinate, value bits)
-//                                 of each document, the vector storage S of Alg. 7
-//   fwd_off  uint64 [cap]         first entry of the document in each slot
-//   fwd_len  uint32 [cap]         its number of entries
+//   fwd      uint2  [entries]     forward store (optional, DevForward): (coordinate,
+//                                 value bits) of each document, the vector storage S
+//                                 of Alg. 7; per slot its first entry (uint64) and
+//                                 entry count (uint32)
 //
 // Bitmaps are interleaved in groups of 256 slots so that a 64-bit word is a
 // wavefront lane mask while each lane still reads 4 adjacent sketch values at
@@ -40,10 +40,16 @@ struct DevIndex {
   float *L;
   uint32_t *slot2id;
   uint32_t *bucket;
-  uint2 *fwd;         // null without a forward store
-  uint64_t *fwd_off;
-  uint32_t *fwd_len;
   uint32_t dim, m, h, cap, W;
+};
+
+// Forward store (optional), kept out of DevIndex: the scoring kernel's
+// argument block stays small, which keeps its register use (and occupancy)
+// where it is without one.
+struct DevForward {
+  uint2 *ent;        // (coordinate, value bits) entries; null without a forward store
+  uint64_t *off;     // [cap] first entry of each slot's document
+  uint32_t *len;     // [cap] its number of entries
 };
 
 // Prepared queries (Alg. 6 first steps): entry e of query q sits at qptr[q] + i
@@ -127,8 +133,8 @@ __host__ __device__ inline float key_value(uint32_t k) {
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,
-                         const uint64_t *indptr, const uint32_t *coords, const float *vals, const uint64_t *doc_off,
-                         hipStream_t s);
+                         const uint64_t *indptr, const uint32_t *coords, const float *vals, const DevForward &fw,
+                         const uint64_t *doc_off, hipStream_t s);
 hipError_t launch_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const uint32_t *slots,
                              const uint32_t *seqs, int is_insert, hipStream_t s);
 hipError_t launch_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap, hipStream_t s);
@@ -141,9 +147,12 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStre
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t s);
+// the final top-k of each query straight from all its tile groups (radix select)
+hipError_t launch_select(const MergeArgs &a, hipStream_t s);
+constexpr uint32_t kSelectMinK = 64;  // k from which the select replaces the merge levels
 // Alg. 7 ranking of the merged k' candidates of each query.
 struct RerankArgs {
-  DevIndex ix;
+  DevForward fw;
   QueryDesc qd;
   uint32_t q0;              // first query of this launch
   uint32_t kprime, k;

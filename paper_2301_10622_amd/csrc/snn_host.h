@@ -185,6 +185,7 @@ struct snn_index {
   uint32_t cap = 0, W = 0;
   hipStream_t stream = nullptr;
   snn::DevIndex dev{};
+  snn::DevForward fw{};  // forward store (SNN_FORWARD_STORE)
 
   // slot store
   std::unordered_map<uint32_t, uint32_t> id2slot;

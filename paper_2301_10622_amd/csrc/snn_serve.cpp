@@ -251,7 +251,8 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
     HIP_TRY(ix, launch_serve_mark(ix->vis, ix->dirty, cnt, dp, dp + 2 * cnt, 1, M), "serve mark");
     HIP_TRY(ix,
             launch_insert(ix->dev, cnt, dp, dp + cnt, (const uint64_t *)i_ptr.p + first_ins, (const uint32_t *)i_c.p,
-                          (const float *)i_v.p, ix->has_fwd ? (const uint64_t *)((char *)dp + o_off) : nullptr, M),
+                          (const float *)i_v.p, ix->fw, ix->has_fwd ? (const uint64_t *)((char *)dp + o_off) : nullptr,
+                          M),
             "serve insert");
     HIP_TRY(ix, hipFreeAsync(dp, M), "serve upload");
     g_slots.clear();
