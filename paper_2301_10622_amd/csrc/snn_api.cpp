@@ -472,16 +472,12 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   const size_t o_q = o; o += al((size_t)total * 4);
   const size_t o_b = o; o += al((size_t)total * 4 * h);
   const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
-  const size_t o_cc2 = o; o += al((size_t)nq * tiles * 4);
   const size_t o_queue = o; o += al(64 * 4);
   const size_t o_qlist = o; o += al((size_t)nq * 4);
   const size_t o_nlist = o; o += al(4);
   const size_t o_stats = o; o += al(32);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
-  const uint32_t F = merge_fanin(k);
-  const uint32_t g1 = (tiles + F - 1) / F;
   HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
-  HIP_TRY(this, W.cand2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 8 + 64, stream), "candidate buffer");
   char *p = (char *)W.ws.p;
   w.cnt = (uint32_t *)(p + o_cnt);
   w.status = (uint32_t *)(p + o_status);
@@ -492,21 +488,17 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.q = (float *)(p + o_q);
   w.b = (uint32_t *)(p + o_b);
   w.cand_cnt = (uint32_t *)(p + o_cc);
-  w.cand_cnt2 = (uint32_t *)(p + o_cc2);
   w.queue = (uint32_t *)(p + o_queue);
   w.qlist = (uint32_t *)(p + o_qlist);
   w.nlist = (uint32_t *)(p + o_nlist);
   w.stats = (unsigned long long *)(p + o_stats);
   w.cand = (uint64_t *)W.cand.p;
-  w.cand2 = (uint64_t *)W.cand2.p;
-  w.cslot = w.cslot2 = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
+  w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
   if (slots) {
     HIP_TRY(this, W.cslot.ensure((size_t)nq * tiles * k * 4 + 64, stream), "candidate slots");
-    HIP_TRY(this, W.cslot2.ensure((size_t)nq * std::max<uint32_t>(g1, 1) * k * 4 + 64, stream), "candidate slots");
     HIP_TRY(this, W.rr.ensure((size_t)nq * k * 12 + (size_t)nq * 4 + 1024, stream), "re-rank candidates");
     w.cslot = (uint32_t *)W.cslot.p;
-    w.cslot2 = (uint32_t *)W.cslot2.p;
     w.rr_ids = (uint32_t *)W.rr.p;
     w.rr_sc = (float *)(w.rr_ids + (size_t)nq * k);
     w.rr_slot = (uint32_t *)(w.rr_sc + (size_t)nq * k);
@@ -515,89 +507,29 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   return SNN_OK;
 }
 
-uint32_t snn_index::merge_fanin(uint32_t k) const {
-  uint32_t F = (uint32_t)kMergeCap / std::max<uint32_t>(k, 1);
-  if (F > 256) F = 256;
-  if (F < 2) F = 2;
-  return F;
-}
-
-// Enqueue the merge levels of one merge job.
+// Enqueue the selection of each query's top-k over all of its tile groups.
 snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStream_t s) {
-  if (j.k >= kSelectMinK) {
-    // large k: one radix-select pass over every tile group of each query
-    MergeArgs m{};
-    m.groups_in = j.tiles;
-    m.fanin = j.tiles;
-    m.groups_out = 1;
-    m.kmax = j.k;
-    m.kq = j.kq;
-    m.keff = j.keff;
-    m.in = w.cand;
-    m.in_cnt = w.cand_cnt;
-    m.status = w.status;
-    m.qlist = j.qlist;
-    m.nlist = j.nlist;
-    m.emitted = j.emitted;
-    m.in_slot = j.slots ? w.cslot : nullptr;
-    m.res_ids = j.res_ids;
-    m.res_scores = j.res_scores;
-    m.res_cnt = j.res_cnt;
-    m.res_slots = j.res_slots;
-    m.fallback = j.set_fallback ? w.fallback : nullptr;
-    for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
-      m.q0 = j.q0 + c0;
-      m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
-      HIP_TRY(this, launch_select(m, s), "select kernel");
-    }
-    return SNN_OK;
-  }
-  const uint32_t F = merge_fanin(j.k);
-  uint32_t G = j.tiles;
-  const uint64_t *in = w.cand;
-  const uint32_t *in_cnt = w.cand_cnt;
-  uint64_t *bufs[2] = {w.cand2, w.cand};
-  uint32_t *cnts[2] = {w.cand_cnt2, w.cand_cnt};
-  uint32_t *sbufs[2] = {w.cslot2, w.cslot};
-  const uint32_t *in_slot = j.slots ? w.cslot : nullptr;
-  int lvl = 0;
-  for (;;) {
-    MergeArgs m{};
-    m.in_slot = in_slot;
-    m.groups_in = G;
-    m.fanin = std::min(F, G);
-    m.groups_out = (G + m.fanin - 1) / m.fanin;
-    m.kmax = j.k;
-    m.kq = j.kq;
-    m.keff = j.keff;
-    m.in = in;
-    m.in_cnt = in_cnt;
-    m.status = w.status;
-    m.qlist = j.qlist;
-    m.nlist = j.nlist;
-    m.emitted = lvl == 0 ? j.emitted : nullptr;
-    if (m.groups_out > 1) {
-      m.out = bufs[lvl & 1];
-      m.out_cnt = cnts[lvl & 1];
-      if (j.slots) m.out_slot = sbufs[lvl & 1];
-    } else {
-      m.res_ids = j.res_ids;
-      m.res_scores = j.res_scores;
-      m.res_cnt = j.res_cnt;
-      m.res_slots = j.res_slots;
-      m.fallback = j.set_fallback ? w.fallback : nullptr;
-    }
-    for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
-      m.q0 = j.q0 + c0;
-      m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
-      HIP_TRY(this, launch_merge(m, s), "merge kernel");
-    }
-    if (m.groups_out == 1) break;
-    in = m.out;
-    in_cnt = m.out_cnt;
-    in_slot = m.out_slot;
-    G = m.groups_out;
-    ++lvl;
+  SelectArgs m{};
+  m.groups_in = j.tiles;
+  m.kmax = j.k;
+  m.kq = j.kq;
+  m.keff = j.keff;
+  m.in = w.cand;
+  m.in_cnt = w.cand_cnt;
+  m.status = w.status;
+  m.qlist = j.qlist;
+  m.nlist = j.nlist;
+  m.emitted = j.emitted;
+  m.in_slot = j.slots ? w.cslot : nullptr;
+  m.res_ids = j.res_ids;
+  m.res_scores = j.res_scores;
+  m.res_cnt = j.res_cnt;
+  m.res_slots = j.res_slots;
+  m.fallback = j.set_fallback ? w.fallback : nullptr;
+  for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
+    m.q0 = j.q0 + c0;
+    m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
+    HIP_TRY(this, launch_select(m, s), "select kernel");
   }
   return SNN_OK;
 }
@@ -787,7 +719,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.ptr = d_ptr; key.c = d_c; key.v = d_v; key.ids = d_ids; key.sc = d_sc; key.cnt = d_cnt;
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;
   Workspace &W = o.wsp ? *o.wsp : wsp;
-  key.ws = W.ws.p; key.cand = W.cand.p; key.cand2 = W.cand2.p; key.qseq = o.qseq; key.ebase = o.ebase;
+  key.ws = W.ws.p; key.cand = W.cand.p; key.qseq = o.qseq; key.ebase = o.ebase;
   key.rerank_k = o.rerank_k;
   key.hash_cap = o.hash_cap;
   key.cslot = W.cslot.p;

@@ -90,32 +90,26 @@ struct TileArgs {
   unsigned long long *nselect;  // += 1 per tile that ran the radix select (nullable)
 };
 
-struct MergeArgs {
+// Final selection of each query's top-k over all of its tile groups.
+struct SelectArgs {
   uint32_t nq;
   uint32_t q0;
-  uint32_t groups_in;   // groups per query in the input
-  uint32_t fanin;       // input groups merged by one workgroup
-  uint32_t groups_out;  // groups per query in the output (1 = final)
-  uint32_t kmax;        // stride of a group
+  uint32_t groups_in;   // tile groups per query
+  uint32_t kmax;        // stride of a group and of a result row
   const uint32_t *kq;   // per-query k (nullable)
   const uint32_t *keff; // per-query required count for the filter check (nullable)
-  const uint64_t *in;
-  const uint32_t *in_cnt;
-  uint64_t *out;        // next level (when groups_out > 1)
-  uint32_t *out_cnt;
-  uint32_t *res_ids;    // final level: [nq][kmax]
+  const uint64_t *in;     // [nq][groups_in][kmax] keys
+  const uint32_t *in_cnt; // [nq][groups_in]
+  uint32_t *res_ids;    // [nq][kmax]
   float *res_scores;
   uint32_t *res_cnt;    // [nq]
   uint32_t *fallback;   // [nq] set to 1 when fewer than keff candidates survived
   const uint32_t *status; // [nq] malformed queries produce 0 results
   const uint32_t *qlist;  // query list (nullable), as in TileArgs
   const uint32_t *nlist;
-  unsigned long long *emitted; // first level only (nullable): += candidates read
-  // candidate slots carried with the keys (nullable): in / out per level, and
-  // the final level's [nq][kmax] slots of the results
-  const uint32_t *in_slot;
-  uint32_t *out_slot;
-  uint32_t *res_slots;
+  unsigned long long *emitted; // nullable: += candidates read
+  const uint32_t *in_slot;     // candidate slots, layout of `in` (nullable)
+  uint32_t *res_slots;         // [nq][kmax] slots of the results (with in_slot)
 };
 
 __host__ __device__ inline uint32_t slot_word(uint32_t slot) { return ((slot >> 8) << 2) | (slot & 3u); }
@@ -146,10 +140,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
-hipError_t launch_merge(const MergeArgs &a, hipStream_t s);
 // the final top-k of each query straight from all its tile groups (radix select)
-hipError_t launch_select(const MergeArgs &a, hipStream_t s);
-constexpr uint32_t kSelectMinK = 64;  // k from which the select replaces the merge levels
+hipError_t launch_select(const SelectArgs &a, hipStream_t s);
 // Alg. 7 ranking of the merged k' candidates of each query.
 struct RerankArgs {
   DevForward fw;

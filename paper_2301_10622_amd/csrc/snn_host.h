@@ -30,14 +30,12 @@ struct PinBuf {
 
 // Device buffers of one in-flight search batch.
 struct Workspace {
-  DevBuf ws, cand, cand2;
-  DevBuf cslot, cslot2, rr;  // re-rank: candidate slots per level, the merged k' candidates
+  DevBuf ws, cand;
+  DevBuf cslot, rr;  // re-rank: candidate slots, the selected k' candidates
   void release() {
     ws.release();
     cand.release();
-    cand2.release();
     cslot.release();
-    cslot2.release();
     rr.release();
   }
 };
@@ -46,10 +44,10 @@ struct SearchWs {
   uint32_t *cnt = nullptr, *status = nullptr, *thr = nullptr, *fallback = nullptr, *keff = nullptr;
   uint32_t *j = nullptr, *b = nullptr;
   float *q = nullptr;
-  uint32_t *cand_cnt = nullptr, *cand_cnt2 = nullptr, *queue = nullptr;
-  uint64_t *cand = nullptr, *cand2 = nullptr;
+  uint32_t *cand_cnt = nullptr, *queue = nullptr;
+  uint64_t *cand = nullptr;
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
-  uint32_t *cslot = nullptr, *cslot2 = nullptr;  // re-rank: slot of each candidate, per merge level
+  uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
   uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' merged candidates
   float *rr_sc = nullptr;
   unsigned long long *stats = nullptr;          // candidates emitted, selecting tiles (main, fallback pass)
@@ -90,13 +88,13 @@ struct SearchOpts {
   bool no_graph = false;
 };
 
-// One merge pass (all levels) over the tile candidates of queries q0 .. q0 + nqm
+// One selection pass over the tile candidates of queries q0 .. q0 + nqm
 // (or of the listed queries, when qlist is set).
 struct MergeJob {
   uint32_t q0 = 0, nqm = 0, tiles = 0, k = 0;
   const uint32_t *kq = nullptr, *keff = nullptr;
   uint32_t *res_ids = nullptr, *res_cnt = nullptr, *res_slots = nullptr;
-  bool slots = false;  // carry the candidates' slots (cslot / cslot2) through the levels
+  bool slots = false;  // carry the candidates' slots (cslot) to the results
   float *res_scores = nullptr;
   const uint32_t *qlist = nullptr, *nlist = nullptr;
   unsigned long long *emitted = nullptr;
@@ -120,7 +118,7 @@ struct GraphKey {
   uint32_t nq, k, mode, R, grid, tiles;
   uint64_t total;
   bool persistent, prof;
-  const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *cand2, *qseq;
+  const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *qseq;
   const void *lX, *ly, *lthr, *lkeff, *lPb, *ltab;
   uint32_t ldelta, lkeff_v, rerank_k, hash_cap;
   const void *cslot, *rr, *fwd;
@@ -133,7 +131,7 @@ struct GraphKey {
            cslot == o.cslot && rr == o.rr && fwd == o.fwd &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
-           ws == o.ws && cand == o.cand && cand2 == o.cand2 && qseq == o.qseq && ebase == o.ebase &&
+           ws == o.ws && cand == o.cand && qseq == o.qseq && ebase == o.ebase &&
            stream == o.stream;
   }
 };
@@ -245,7 +243,6 @@ struct snn_index {
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
   snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, bool slots,
                                snn::SearchWs &w, snn::Workspace &W, hipStream_t s);
-  uint32_t merge_fanin(uint32_t k) const;
   snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
                          uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p,

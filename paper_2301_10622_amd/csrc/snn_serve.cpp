@@ -216,10 +216,8 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
   const uint32_t tile_docs_est = (uint32_t)kBlock * ix->tune.R_batch;
   auto batch_bytes = [&](uint32_t q0, uint32_t q1, uint32_t km) -> uint64_t {
     const uint32_t tiles = std::max<uint32_t>(1, (ix->next_fresh + tile_docs_est - 1) / tile_docs_est + 1);
-    const uint32_t F = ix->merge_fanin(km);
     const uint64_t nq = q1 - q0;
-    return nq * tiles * km * 8ull + nq * ((tiles + F - 1) / F) * km * 8ull + (hs_ptr[q1] - hs_ptr[q0]) * 16ull +
-           nq * (64ull + tiles * 8ull + km * 8ull);
+    return nq * tiles * km * 8ull + (hs_ptr[q1] - hs_ptr[q0]) * 16ull + nq * (64ull + tiles * 4ull + km * 8ull);
   };
 
   const auto t0 = Clock::now();
