@@ -58,11 +58,11 @@ def lib():
         L.orc_free.argtypes = [P]
         L.orc_postings.restype = u64
         L.orc_postings.argtypes = [P]
-        L.orc_score_all.argtypes = [P, u32, P, P, i32, P, P]
+        L.orc_score_all.argtypes = [P, u32, P, P, i32, u32, P, P]
         L.orc_find_largest.restype = u32
         L.orc_find_largest.argtypes = [u32, P, P, P, u32, P]
-        L.orc_search.argtypes = [P, u32, P, P, P, u32, i32, i32, P, P, P, P]
-        L.orc_rerank.argtypes = [P, u32, P, P, P, u32, u32, i32, P, P, P, P]
+        L.orc_search.argtypes = [P, u32, P, P, P, u32, i32, u32, i32, P, P, P, P]
+        L.orc_rerank.argtypes = [P, u32, P, P, P, u32, u32, u32, i32, P, P, P, P]
         L.orc_max_threads.restype = i32
         L.orc_features.argtypes = [u32, P, P, u64, P]
         L.orc_mlp_forward.argtypes = [u32, P, P, P, P, P, P, P, P]
@@ -162,14 +162,16 @@ class Index:
     def postings(self) -> int:
         return int(lib().orc_postings(self._h))
 
-    def score_all(self, qc, qv, exact: bool = False):
+    def score_all(self, qc, qv, exact: bool = False, max_coords: int = 0):
+        """Scores of every document (Alg. 6 estimate or exact); max_coords > 0
+        stops after that many coordinates in the sorted order (anytime)."""
         qc, qv = _u32(qc), _f32(qv)
         s = np.zeros(max(self.N, 1))
         a = np.zeros(max(self.N, 1))
-        lib().orc_score_all(self._h, len(qc), _p(qc), _p(qv), 1 if exact else 0, _p(s), _p(a))
+        lib().orc_score_all(self._h, len(qc), _p(qc), _p(qv), 1 if exact else 0, max_coords, _p(s), _p(a))
         return s[: self.N], a[: self.N]
 
-    def search(self, queries, k: int, exact: bool = False, threads: int = 1):
+    def search(self, queries, k: int, exact: bool = False, threads: int = 1, max_coords: int = 0):
         qp = np.ascontiguousarray(queries.indptr, dtype=np.int64)
         qc, qv = _u32(queries.coords), _f32(queries.vals)
         nq = len(qp) - 1
@@ -177,12 +179,13 @@ class Index:
         sc = np.zeros((nq, max(k, 1)))
         ab = np.zeros((nq, max(k, 1)))
         cnt = np.zeros(nq, dtype=np.uint32)
-        lib().orc_search(self._h, nq, _p(qp), _p(qc), _p(qv), k, 1 if exact else 0, threads,
+        lib().orc_search(self._h, nq, _p(qp), _p(qc), _p(qv), k, 1 if exact else 0, max_coords, threads,
                          _p(ids), _p(sc), _p(ab), _p(cnt))
         return ids[:, :k], sc[:, :k], ab[:, :k], cnt
 
-    def rerank(self, queries, k: int, kprime: int, threads: int = 1):
-        """Alg. 7 with k' >= k: (ids, exact scores, sum |q_j x_j|, counts)."""
+    def rerank(self, queries, k: int, kprime: int, threads: int = 1, max_coords: int = 0):
+        """Alg. 7 with k' >= k: (ids, exact scores, sum |q_j x_j|, counts);
+        max_coords > 0 makes the candidate scoring anytime."""
         qp = np.ascontiguousarray(queries.indptr, dtype=np.int64)
         qc, qv = _u32(queries.coords), _f32(queries.vals)
         nq = len(qp) - 1
@@ -190,7 +193,8 @@ class Index:
         sc = np.zeros((nq, max(k, 1)))
         ab = np.zeros((nq, max(k, 1)))
         cnt = np.zeros(nq, dtype=np.uint32)
-        lib().orc_rerank(self._h, nq, _p(qp), _p(qc), _p(qv), k, kprime, threads, _p(ids), _p(sc), _p(ab), _p(cnt))
+        lib().orc_rerank(self._h, nq, _p(qp), _p(qc), _p(qv), k, kprime, max_coords, threads, _p(ids), _p(sc), _p(ab),
+                         _p(cnt))
         return ids[:, :k], sc[:, :k], ab[:, :k], cnt
 
 

@@ -312,11 +312,15 @@ void orc_free(orc_index *ix) {
 uint64_t orc_postings(const orc_index *ix) { return ix->list_ptr[ix->n]; }
 
 /* Scores of every document for one query. mode 0: Sinnamon estimate (Alg. 6),
- * mode 1: exact (Alg. 2). abs_sum (may be NULL) receives sum |term| per doc. */
+ * mode 1: exact (Alg. 2). abs_sum (may be NULL) receives sum |term| per doc.
+ * max_coords > 0 is the anytime budget: the walk over the sorted query
+ * coordinates stops after that many (the break of Alg. 4 and Alg. 6 taken
+ * after a fixed number of coordinates instead of a time budget). */
 void orc_score_all(const orc_index *ix, uint32_t qn, const uint32_t *qc, const float *qv, int mode,
-                   double *scores, double *abs_sum) {
+                   uint32_t max_coords, double *scores, double *abs_sum) {
   orc_qterm *qs = (orc_qterm *)malloc(sizeof(orc_qterm) * (qn ? qn : 1));
   uint32_t t = orc_sorted_query(qn, qc, qv, qs);
+  if (max_coords > 0 && max_coords < t) t = max_coords;
   for (uint32_t i = 0; i < ix->N; ++i) scores[i] = 0.0;
   if (abs_sum)
     for (uint32_t i = 0; i < ix->N; ++i) abs_sum[i] = 0.0;
@@ -423,8 +427,8 @@ uint32_t orc_find_largest(uint32_t N, const double *scores, const uint32_t *ids,
 /* Batched top-k over the index. mode 0: estimate, 1: exact. OpenMP over
  * queries when threads > 1. Outputs are k per query; counts = min(k, N). */
 void orc_search(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uint32_t *qc, const float *qv,
-                uint32_t k, int mode, int threads, uint32_t *out_ids, double *out_scores, double *out_abs,
-                uint32_t *out_counts) {
+                uint32_t k, int mode, uint32_t max_coords, int threads, uint32_t *out_ids, double *out_scores,
+                double *out_abs, uint32_t *out_counts) {
 #ifdef _OPENMP
   if (threads < 1) threads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
@@ -434,7 +438,7 @@ void orc_search(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uin
     double *ab = out_abs ? (double *)malloc(sizeof(double) * (ix->N ? ix->N : 1)) : NULL;
     uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * (k ? k : 1));
     int64_t a = qptr[qi], b = qptr[qi + 1];
-    orc_score_all(ix, (uint32_t)(b - a), qc + a, qv + a, mode, sc, ab);
+    orc_score_all(ix, (uint32_t)(b - a), qc + a, qv + a, mode, max_coords, sc, ab);
     uint32_t c = orc_find_largest(ix->N, sc, ix->ids, NULL, k, pos);
     out_counts[qi] = c;
     for (uint32_t r = 0; r < c; ++r) {
@@ -449,15 +453,16 @@ void orc_search(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uin
 }
 
 /* Ranking with k' >= k (Alg. 7) for a batch of queries. Per query: the
- * Sinnamon scores of every document (Alg. 6); V = FindLargest(scores, k');
+ * Sinnamon scores of every document (Alg. 6, stopped after max_coords sorted
+ * coordinates when max_coords > 0); V = FindLargest(scores, k');
  * s_v = <q, S.Fetch(v)> for v in V, the exact inner product (Eq. 2) of the
  * query with the stored vector; the result is FindLargest({s_v}, k). Both
  * FindLargest calls break ties by the lower external id. out_scores are the
  * exact scores s_v, out_abs the sums of |q_j x_j| over the shared coordinates
  * (the error scale of the comparison tolerance); counts = min(k, k', N). */
 void orc_rerank(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uint32_t *qc, const float *qv,
-                uint32_t k, uint32_t kprime, int threads, uint32_t *out_ids, double *out_scores, double *out_abs,
-                uint32_t *out_counts) {
+                uint32_t k, uint32_t kprime, uint32_t max_coords, int threads, uint32_t *out_ids, double *out_scores,
+                double *out_abs, uint32_t *out_counts) {
 #ifdef _OPENMP
   if (threads < 1) threads = 1;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
@@ -471,7 +476,7 @@ void orc_rerank(const orc_index *ix, uint32_t nq, const int64_t *qptr, const uin
     uint32_t *best = (uint32_t *)malloc(sizeof(uint32_t) * (k ? k : 1));
     int64_t a = qptr[qi], b = qptr[qi + 1];
     uint32_t qn = (uint32_t)(b - a);
-    orc_score_all(ix, qn, qc + a, qv + a, 0, sc, NULL);
+    orc_score_all(ix, qn, qc + a, qv + a, 0, max_coords, sc, NULL); /* anytime scoring, then the full q */
     uint32_t nv = orc_find_largest(ix->N, sc, ix->ids, NULL, kprime, V);
     for (uint32_t r = 0; r < nv; ++r) {
       uint32_t d = V[r];

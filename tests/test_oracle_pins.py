@@ -366,6 +366,76 @@ def test_rerank_recall_never_drops_as_kprime_grows(small):
 
 
 # --------------------------------------------------------------------------
+# anytime scoring: a budget of c coordinates in the order of Alg. 6
+# --------------------------------------------------------------------------
+
+def _truncate(qc, qv, c):
+    """The c non-zeros of largest |q_j| (ties: lower j), written out directly."""
+    nz = [(abs(float(v)), int(j), float(v)) for j, v in zip(qc, qv) if v != 0]
+    nz.sort(key=lambda t: (-t[0], t[1]))
+    keep = nz[:c]
+    return np.array([t[1] for t in keep], np.uint32), np.array([t[2] for t in keep], np.float32)
+
+
+def test_anytime_budget_scores_the_largest_coordinates_first():
+    """Stopping after c coordinates equals scoring the query cut to its c
+    entries of largest |q_j| (the order Alg. 6 walks), checked per pair with
+    the doc-at-a-time estimate, for signed data and for budgets 0 (all), 1, a
+    few, and more than the query has."""
+    w = gen.make_small(3, docs=300, queries=6)
+    ix = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    for qi in range(w.queries.rows):
+        qc, qv = w.queries.row(qi)
+        full, _ = ix.score_all(qc, qv)
+        for c in (0, 1, 3, 7, 19, 20, 500):
+            s, a = ix.score_all(qc, qv, max_coords=c)
+            if c == 0 or c >= len(qc):
+                assert np.array_equal(s, full)
+                continue
+            tc, tv = _truncate(qc, qv, c)
+            for i in range(0, w.docs.rows, 7):
+                dc, dv = w.docs.row(i)
+                est = O.pair_est(tc, tv, dc, dv, w.m, w.h, w.hash_seed)
+                assert abs(s[i] - est[0]) <= 1e-12 * max(1.0, est[1]), (qi, c, i)
+
+
+def test_anytime_nonnegative_partial_scores_rise_and_bound_exact():
+    """Non-negative data: each further coordinate adds a non-negative term, so
+    the anytime score never falls as the budget grows, and it is at least the
+    exact inner product over the coordinates processed so far (the upper-bound
+    remark of Section 4.2, Theorem 1 applied to the processed part)."""
+    rng = np.random.default_rng(8)
+    docs = gen.sparse_rows(81, 400, 300, 1.1, rng.integers(5, 40, 400), "exp")
+    qs = gen.sparse_rows(82, 5, 300, 1.1, np.full(5, 25), "exp")
+    ix = O.Index(docs, 300, 8, 1, 3)
+    for qi in range(qs.rows):
+        qc, qv = qs.row(qi)
+        prev = np.zeros(docs.rows)
+        for c in range(1, 26):
+            s, _ = ix.score_all(qc, qv, max_coords=c)
+            assert np.all(s >= prev - 1e-12)
+            tc, tv = _truncate(qc, qv, c)
+            ex, _ = ix.score_all(tc, tv, exact=True)
+            assert np.all(s >= ex - 1e-12)
+            prev = s
+
+
+def test_anytime_rerank_uses_budgeted_candidates_and_full_exact_scores(small):
+    """Alg. 4 / Alg. 7 with a budget: candidates by the budgeted scores, exact
+    inner products with the whole query."""
+    w, ix = small
+    D = _dense(w)
+    ids, sc, ab, cnt = ix.rerank(w.queries, 10, 60, max_coords=5)
+    for qi in range(w.queries.rows):
+        qc, qv, q = _dense_q(w, qi)
+        est, _ = ix.score_all(qc, qv, max_coords=5)
+        V = _brute_topk(est, np.arange(w.docs.rows), 60)
+        best = [V[p] for p in _brute_topk(D[V] @ q, np.array(V), 10)]
+        assert list(ids[qi][: cnt[qi]]) == best
+        np.testing.assert_allclose(sc[qi][: cnt[qi]], D[best] @ q, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
 # MLP of the learned filter: gradients against central differences
 # --------------------------------------------------------------------------
 
