@@ -139,6 +139,40 @@ snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indp
                                 const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
                                 float *out_scores, uint32_t *out_counts, void *stream);
 
+/* Options of one batch search (all the forms above in one call):
+ *   mode        SNN_MODE_PLAIN, SNN_MODE_BATCHED or SNN_MODE_LEARNED
+ *   k_prime     0: ranking by the Sinnamon scores (Alg. 7 with k' = k, i.e.
+ *               Alg. 3); k <= k_prime <= 4096: Alg. 7 with k_prime candidates
+ *               re-scored exactly (SNN_MODE_BATCHED and an index with
+ *               SNN_FORWARD_STORE)
+ *   max_coords  0: every query coordinate is scored; c > 0: the anytime
+ *               variant, scoring stops after the first c coordinates in the
+ *               order of Alg. 6 (|q_j| descending, ties by the lower j). This
+ *               is the time budget T of Alg. 4 / Alg. 6 expressed as a count
+ *               of coordinates, so results do not depend on timing. The
+ *               re-rank of Alg. 7 still uses every coordinate of q.
+ *   reserved    must be 0 */
+typedef struct {
+  uint32_t mode;
+  uint32_t k_prime;
+  uint32_t max_coords;
+  uint32_t reserved;
+} snn_search_params;
+
+/* Device-pointer batch search with options; arguments otherwise as in
+ * snn_search_batch_dev. Errors: SNN_E_INVALID (k = 0 or > 4096, nq = 0, an
+ * unknown mode, 0 < k' < k, k' > 4096, re-rank outside SNN_MODE_BATCHED or
+ * without a forward store, reserved != 0), SNN_E_NOMEM, SNN_E_DEVICE. */
+snn_status snn_search_ex_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                             const uint32_t *coords, const float *vals, uint32_t k, const snn_search_params *params,
+                             uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream);
+
+/* The same from host buffers (CSR queries as in snn_search_batch); returns
+ * after the results are on the host. */
+snn_status snn_search_ex(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                         const float *vals, uint32_t k, const snn_search_params *params, uint32_t *out_ids,
+                         float *out_scores, uint32_t *out_counts);
+
 /* Ranking with k' >= k (Alg. 7): the k_prime documents with the largest
  * Sinnamon scores are fetched from the forward store, scored exactly (the
  * inner product of Eq. 2, FP32 sums) and the k best by exact score are

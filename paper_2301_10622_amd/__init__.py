@@ -31,7 +31,8 @@ FORWARD_STORE = 1  # snn_config.flags: keep the vectors on the device (re-rankin
 EXPORTS = [
     "snn_create", "snn_destroy", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch",
     "snn_search", "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
-    "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_bucket_table",
+    "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_search_ex", "snn_search_ex_dev",
+                     "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
@@ -95,6 +96,11 @@ class ServeReport(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
+class SearchParams(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_uint32), ("k_prime", ctypes.c_uint32), ("max_coords", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
 class BatchWork(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_uint64), ("candidates_fallback", ctypes.c_uint64),
                 ("selects", ctypes.c_uint64), ("selects_fallback", ctypes.c_uint64)]
@@ -129,6 +135,8 @@ def lib():
         L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
         L.snn_search_rerank.argtypes = [P, u32, P, P, P, u32, u32, P, P, P]
+        L.snn_search_ex.argtypes = [P, u32, P, P, P, u32, P, P, P, P]
+        L.snn_search_ex_dev.argtypes = [P, u32, P, u64, P, P, u32, P, P, P, P, P]
         L.snn_search_rerank_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_work.argtypes = [P, P]
         L.snn_bucket_table.argtypes = [P, P]
@@ -152,7 +160,8 @@ def lib():
         L.snn_last_error.restype = ctypes.c_char_p
         for name in ("snn_create", "snn_insert", "snn_insert_batch", "snn_delete", "snn_delete_batch", "snn_search",
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
-                     "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_bucket_table",
+                     "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_search_ex", "snn_search_ex_dev",
+    "snn_bucket_table",
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
@@ -264,6 +273,42 @@ class Index:
         sc = np.zeros((nq, k), np.float32)
         cnt = np.zeros(nq, np.uint32)
         self._check(lib().snn_search_rerank(self._h, nq, _p(ip), _p(c), _p(v), k, k_prime, _p(ids), _p(sc), _p(cnt)))
+        return ids, sc, cnt
+
+    def search_ex(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, k_prime: int = 0,
+                  max_coords: int = 0):
+        """Batch search from host buffers with options: mode, Alg. 7 width k'
+        and the anytime coordinate budget. Returns (ids, scores, counts)."""
+        ip = np.ascontiguousarray(indptr, dtype=np.uint64)
+        c = np.ascontiguousarray(coords, dtype=np.uint32)
+        v = np.ascontiguousarray(vals, dtype=np.float32)
+        nq = len(ip) - 1
+        ids = np.zeros((nq, k), np.uint32)
+        sc = np.zeros((nq, k), np.float32)
+        cnt = np.zeros(nq, np.uint32)
+        prm = SearchParams(mode, k_prime, max_coords, 0)
+        self._check(lib().snn_search_ex(self._h, nq, _p(ip), _p(c), _p(v), k, ctypes.byref(prm), _p(ids), _p(sc),
+                                        _p(cnt)))
+        return ids, sc, cnt
+
+    def search_ex_dev(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, k_prime: int = 0,
+                      max_coords: int = 0, out=None, stream=None, total: Optional[int] = None):
+        """Device tensors in and out, with the options of search_ex."""
+        nq = indptr.numel() - 1
+        if total is None:
+            total = int(coords.numel())
+        dev = indptr.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev),
+                   torch.empty(nq, dtype=torch.int32, device=dev))
+        ids, sc, cnt = out
+        assert indptr.dtype == torch.int64 and coords.dtype == torch.int32 and vals.dtype == torch.float32
+        assert indptr.is_contiguous() and coords.is_contiguous() and vals.is_contiguous()
+        assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
+        prm = SearchParams(mode, k_prime, max_coords, 0)
+        self._check(lib().snn_search_ex_dev(self._h, nq, _tp(indptr), int(total), _tp(coords), _tp(vals), k,
+                                            ctypes.byref(prm), _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
         return ids, sc, cnt
 
     def search_rerank_dev(self, indptr, coords, vals, k: int, k_prime: int, out=None, stream=None,

@@ -179,7 +179,10 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStre
 //   drop zero values (nz), reject coordinates >= dim, non-finite values and
 //   duplicate coordinates, sort by |q_j| descending with ties to the lower j
 //   (the order Alg. 6 walks the coordinates in), and look up the h buckets
-//   K = {pi_o(j)} of every coordinate.
+//   K = {pi_o(j)} of every coordinate. cnt[q], the number of coordinates the
+//   scoring walks, is cut to max_coords when that is smaller (the anytime
+//   budget; every entry is still written), and nz_full[q] (nullable) gets the
+//   whole count for the exact re-rank.
 // Sort keys are 64-bit: high word ~|q|bits (ascending = |q| descending), low
 // word (j << 1) | sign, so equal magnitudes fall back to the lower coordinate.
 // ---------------------------------------------------------------------------
@@ -202,7 +205,8 @@ __device__ inline void bitonic_sort_u64_asc(uint64_t *s, int n) {
 }
 
 __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const uint32_t *__restrict__ coords,
-                                              const float *__restrict__ vals) {
+                                              const float *__restrict__ vals, uint32_t max_coords,
+                                              uint32_t *__restrict__ nz_full) {
   __shared__ uint64_t keys[kPrepCap];
   __shared__ uint32_t bad;
   __shared__ uint32_t nz;
@@ -218,6 +222,7 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     if (threadIdx.x == 0) {
       qd.cnt[q] = 0;
       qd.status[q] = 1;
+      if (nz_full) nz_full[q] = 0;
     }
     return;
   }
@@ -257,8 +262,9 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
     }
     if (t == 0) {
-      qd.cnt[q] = bad ? 0u : nz;
+      qd.cnt[q] = bad ? 0u : min(nz, max_coords);
       qd.status[q] = bad ? 1u : 0u;
+      if (nz_full) nz_full[q] = bad ? 0u : nz;
     }
     return;
   }
@@ -295,6 +301,7 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     if (threadIdx.x == 0) {
       qd.cnt[q] = 0;
       qd.status[q] = 1;
+      if (nz_full) nz_full[q] = 0;
     }
     return;
   }
@@ -322,15 +329,17 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
   }
   if (threadIdx.x == 0) {
-    qd.cnt[q] = cnt;
+    qd.cnt[q] = min(cnt, max_coords);
     qd.status[q] = 0;
+    if (nz_full) nz_full[q] = cnt;
   }
 }
 
 hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
-                       hipStream_t s) {
+                       uint32_t max_coords, uint32_t *nz_full, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_prep, dim3(nq), dim3(256), 0, s, ix, qd, coords, vals);
+  hipLaunchKernelGGL(k_prep, dim3(nq), dim3(256), 0, s, ix, qd, coords, vals, max_coords ? max_coords : 0xFFFFFFFFu,
+                     nz_full);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
   float *hv = (float *)(hk + cap);                       // [cap] values
   const uint32_t q = a.q0 + blockIdx.x;
   const uint32_t n = a.cand_cnt[q];
-  const uint32_t ne = a.qd.status[q] ? 0u : a.qd.cnt[q];
+  const uint32_t ne = a.qd.status[q] ? 0u : a.nz_full[q];  // the exact score uses every coordinate
   const uint64_t e0 = a.qd.qptr[q] - a.qd.ebase;
   const int tid = threadIdx.x;
   if (2u * ne > cap) {  // the launcher sizes the table for every query; never taken

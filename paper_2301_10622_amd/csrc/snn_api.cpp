@@ -476,6 +476,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   const size_t o_qlist = o; o += al((size_t)nq * 4);
   const size_t o_nlist = o; o += al(4);
   const size_t o_stats = o; o += al(32);
+  const size_t o_nz = o; o += al((size_t)nq * 4);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
   HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
   char *p = (char *)W.ws.p;
@@ -492,6 +493,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.qlist = (uint32_t *)(p + o_qlist);
   w.nlist = (uint32_t *)(p + o_nlist);
   w.stats = (unsigned long long *)(p + o_stats);
+  w.nz_full = (uint32_t *)(p + o_nz);
   w.cand = (uint64_t *)W.cand.p;
   w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
@@ -552,7 +554,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
             "mlp forward");
     HIP_TRY(this, launch_threshold(p.nq, lp->yhat, lp->delta, lp->keff_value, lp->thr, lp->keff, s), "threshold");
   }
-  HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, s), "prep kernel");
+  HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, o.max_coords, w.nz_full, s), "prep kernel");
   const uint32_t *thr_init = lp ? lp->thr : o.thr_init;
   const uint32_t *keff = lp ? lp->keff : o.keff;
   if (thr_init) {
@@ -642,6 +644,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     r.cand_ids = w.rr_ids;
     r.cand_slots = w.rr_slot;
     r.cand_cnt = w.rr_cnt;
+    r.nz_full = w.nz_full;
     r.out_ids = p.d_ids;
     r.out_scores = p.d_sc;
     r.out_cnt = p.d_cnt;
@@ -721,6 +724,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   Workspace &W = o.wsp ? *o.wsp : wsp;
   key.ws = W.ws.p; key.cand = W.cand.p; key.qseq = o.qseq; key.ebase = o.ebase;
   key.rerank_k = o.rerank_k;
+  key.max_coords = o.max_coords;
   key.hash_cap = o.hash_cap;
   key.cslot = W.cslot.p;
   key.rr = W.rr.p;
@@ -765,11 +769,47 @@ static uint32_t rerank_hash_cap(uint64_t max_nnz) {
   return cap;
 }
 
-// Host-buffer batch search: validate, stage, search (re-ranked when kprime > 0:
-// k' = kprime candidates, k returned), read back.
+// Arguments every search form shares: k, the mode, the re-rank width and the
+// anytime budget.
+static snn_status check_params(snn_index *ix, uint32_t k, const snn_search_params &p) {
+  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
+  if (p.mode > SNN_MODE_LEARNED) return ix->fail(SNN_E_INVALID, "search: unknown mode %u", p.mode);
+  if (p.reserved != 0) return ix->fail(SNN_E_INVALID, "search: reserved field must be 0");
+  if (p.k_prime != 0) {
+    if (p.k_prime < k) return ix->fail(SNN_E_INVALID, "re-rank: need k <= k' (k = %u, k' = %u)", k, p.k_prime);
+    if (!ix->has_fwd) return ix->fail(SNN_E_INVALID, "re-rank: the index has no forward store (SNN_FORWARD_STORE)");
+    if (p.k_prime > kMaxK) return ix->fail(SNN_E_INVALID, "re-rank: k' must be <= %u", kMaxK);
+    if (p.mode != SNN_MODE_BATCHED) return ix->fail(SNN_E_INVALID, "re-rank: runs in SNN_MODE_BATCHED only");
+  }
+  return SNN_OK;
+}
+
+// One device-resident batch: validated arguments, then the chosen form.
+static snn_status search_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                             const uint32_t *coords, const float *vals, uint32_t k, const snn_search_params &p,
+                             uint64_t max_nnz, uint32_t *out_ids, float *out_scores, uint32_t *out_counts,
+                             hipStream_t s) {
+  ix->last_nq = nq;
+  ix->last_mode = p.mode;
+  if (p.mode == SNN_MODE_LEARNED)
+    return ix->search_learned(nq, indptr, total, coords, vals, k, p.max_coords, out_ids, out_scores, out_counts, s);
+  SearchOpts o;
+  o.max_coords = p.max_coords;
+  uint32_t kb = k;
+  if (p.k_prime != 0) {
+    o.rerank_k = k;
+    o.hash_cap = rerank_hash_cap(max_nnz);
+    kb = p.k_prime;
+  }
+  return ix->run_search(nq, indptr, total, coords, vals, kb, (int)p.mode, out_ids, out_scores, out_counts, s, o);
+}
+
+// Host-buffer batch search: validate, stage, search, read back.
 static snn_status search_host(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
-                              const float *vals, uint32_t k, uint32_t kprime, uint32_t *out_ids, float *out_scores,
-                              uint32_t *out_counts) {
+                              const float *vals, uint32_t k, const snn_search_params &sp, uint32_t *out_ids,
+                              float *out_scores, uint32_t *out_counts) {
+  snn_status st = check_params(ix, k, sp);
+  if (st != SNN_OK) return st;
   if (nq == 0) return SNN_OK;
   if (!indptr || !out_ids || !out_scores || !out_counts) return ix->fail(SNN_E_INVALID, "search: null pointer");
   std::vector<uint32_t> oc, scratch;
@@ -805,13 +845,8 @@ static snn_status search_host(snn_index *ix, uint32_t nq, const uint64_t *indptr
   uint32_t *d_ids = (uint32_t *)(dp + o_out);
   float *d_sc = (float *)(d_ids + (size_t)nq * k);
   uint32_t *d_cnt = (uint32_t *)(d_sc + (size_t)nq * k);
-  SearchOpts o;
-  if (kprime) {
-    o.rerank_k = k;
-    o.hash_cap = rerank_hash_cap(max_len);
-  }
-  snn_status st = ix->run_search(nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v),
-                                 kprime ? kprime : k, SNN_MODE_BATCHED, d_ids, d_sc, d_cnt, s, o);
+  st = search_dev(ix, nq, (uint64_t *)dp, total - base, (uint32_t *)(dp + o_c), (float *)(dp + o_v), k, sp, max_len,
+                  d_ids, d_sc, d_cnt, s);
   if (st != SNN_OK) return st;
   HIP_TRY(ix, hipMemcpyAsync(hp + o_out, d_ids, out_bytes - 64, hipMemcpyDeviceToHost, s), "search readback");
   HIP_TRY(ix, hipStreamSynchronize(s), "search sync");
@@ -824,47 +859,61 @@ static snn_status search_host(snn_index *ix, uint32_t nq, const uint64_t *indptr
   return SNN_OK;
 }
 
+// Device-buffer entry: the common checks of the _dev calls.
+static snn_status search_dev_entry(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                   const uint32_t *coords, const float *vals, uint32_t k, const snn_search_params &p,
+                                   uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream) {
+  snn_status st = check_params(ix, k, p);
+  if (st != SNN_OK) return st;
+  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
+  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
+    return ix->fail(SNN_E_INVALID, "search: null pointer");
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  // no query holds more entries than the batch (the host does not read indptr)
+  return search_dev(ix, nq, indptr, total, coords, vals, k, p, total, out_ids, out_scores, out_counts, s);
+}
+
 extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
                                        const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
                                        uint32_t *out_counts) {
   if (!ix) return SNN_E_INVALID;
-  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
-  return search_host(ix, nq, indptr, coords, vals, k, 0, out_ids, out_scores, out_counts);
-}
-
-static snn_status check_rerank(snn_index *ix, uint32_t k, uint32_t k_prime) {
-  if (!ix->has_fwd) return ix->fail(SNN_E_INVALID, "re-rank: the index has no forward store (SNN_FORWARD_STORE)");
-  if (k == 0 || k_prime < k || k_prime > kMaxK)
-    return ix->fail(SNN_E_INVALID, "re-rank: need 1 <= k <= k' <= %u (k = %u, k' = %u)", kMaxK, k, k_prime);
-  return SNN_OK;
+  return search_host(ix, nq, indptr, coords, vals, k, snn_search_params{SNN_MODE_BATCHED, 0, 0, 0}, out_ids,
+                     out_scores, out_counts);
 }
 
 extern "C" snn_status snn_search_rerank(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
                                         const float *vals, uint32_t k, uint32_t k_prime, uint32_t *out_ids,
                                         float *out_scores, uint32_t *out_counts) {
   if (!ix) return SNN_E_INVALID;
-  snn_status st = check_rerank(ix, k, k_prime);
-  if (st != SNN_OK) return st;
-  return search_host(ix, nq, indptr, coords, vals, k, k_prime, out_ids, out_scores, out_counts);
+  if (k_prime == 0) return ix->fail(SNN_E_INVALID, "re-rank: k' must be >= k");
+  return search_host(ix, nq, indptr, coords, vals, k, snn_search_params{SNN_MODE_BATCHED, k_prime, 0, 0}, out_ids,
+                     out_scores, out_counts);
+}
+
+extern "C" snn_status snn_search_ex(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
+                                    const float *vals, uint32_t k, const snn_search_params *params,
+                                    uint32_t *out_ids, float *out_scores, uint32_t *out_counts) {
+  if (!ix) return SNN_E_INVALID;
+  if (!params) return ix->fail(SNN_E_INVALID, "search: null params");
+  return search_host(ix, nq, indptr, coords, vals, k, *params, out_ids, out_scores, out_counts);
 }
 
 extern "C" snn_status snn_search_rerank_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
                                             const uint32_t *coords, const float *vals, uint32_t k, uint32_t k_prime,
                                             uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream) {
   if (!ix) return SNN_E_INVALID;
-  snn_status st = check_rerank(ix, k, k_prime);
-  if (st != SNN_OK) return st;
-  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
-  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
-    return ix->fail(SNN_E_INVALID, "search: null pointer");
-  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
-  ix->last_nq = nq;
-  ix->last_mode = SNN_MODE_BATCHED;
-  SearchOpts o;
-  o.rerank_k = k;
-  o.hash_cap = rerank_hash_cap(total);  // no query holds more entries than the batch
-  return ix->run_search(nq, indptr, total, coords, vals, k_prime, SNN_MODE_BATCHED, out_ids, out_scores, out_counts,
-                        s, o);
+  if (k_prime == 0) return ix->fail(SNN_E_INVALID, "re-rank: k' must be >= k");
+  return search_dev_entry(ix, nq, indptr, total, coords, vals, k, snn_search_params{SNN_MODE_BATCHED, k_prime, 0, 0},
+                          out_ids, out_scores, out_counts, stream);
+}
+
+extern "C" snn_status snn_search_ex_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                        const uint32_t *coords, const float *vals, uint32_t k,
+                                        const snn_search_params *params, uint32_t *out_ids, float *out_scores,
+                                        uint32_t *out_counts, void *stream) {
+  if (!ix) return SNN_E_INVALID;
+  if (!params) return ix->fail(SNN_E_INVALID, "search: null params");
+  return search_dev_entry(ix, nq, indptr, total, coords, vals, k, *params, out_ids, out_scores, out_counts, stream);
 }
 
 extern "C" snn_status snn_search(snn_index *ix, uint32_t nnz, const uint32_t *coords, const float *vals, uint32_t k,
@@ -877,17 +926,8 @@ extern "C" snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uin
                                            const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode,
                                            uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream) {
   if (!ix) return SNN_E_INVALID;
-  if (k == 0 || k > kMaxK) return ix->fail(SNN_E_INVALID, "search: k must be in 1..%u", kMaxK);
-  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
-  if (mode > SNN_MODE_LEARNED) return ix->fail(SNN_E_INVALID, "search: unknown mode %u", mode);
-  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
-    return ix->fail(SNN_E_INVALID, "search: null pointer");
-  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
-  ix->last_nq = nq;
-  ix->last_mode = mode;
-  if (mode == SNN_MODE_LEARNED)
-    return ix->search_learned(nq, indptr, total, coords, vals, k, out_ids, out_scores, out_counts, s);
-  return ix->run_search(nq, indptr, total, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, SearchOpts{});
+  return search_dev_entry(ix, nq, indptr, total, coords, vals, k, snn_search_params{mode, 0, 0, 0}, out_ids,
+                          out_scores, out_counts, stream);
 }
 
 extern "C" snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks) {

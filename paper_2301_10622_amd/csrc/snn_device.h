@@ -134,8 +134,9 @@ hipError_t launch_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const u
 hipError_t launch_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap, hipStream_t s);
 hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,
                          const uint32_t *coords, int clear_bits, int clear_live, hipStream_t s);
+// max_coords: anytime budget (0 = every coordinate); nz_full (nullable): whole counts
 hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
-                       hipStream_t s);
+                       uint32_t max_coords, uint32_t *nz_full, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
@@ -152,6 +153,7 @@ struct RerankArgs {
   const uint32_t *cand_ids;   // [nq][kprime] from the final merge
   const uint32_t *cand_slots; // [nq][kprime]
   const uint32_t *cand_cnt;   // [nq]
+  const uint32_t *nz_full;    // [nq] non-zeros of each prepared query (all of them, whatever the budget)
   uint32_t *out_ids;        // [nq][k]
   float *out_scores;
   uint32_t *out_cnt;        // [nq]

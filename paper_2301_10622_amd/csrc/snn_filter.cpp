@@ -353,8 +353,8 @@ extern "C" snn_status snn_filter_train(snn_index *ix, uint32_t nq, const uint64_
 // filtered search with fallback
 // ---------------------------------------------------------------------------
 snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
-                                     const float *d_v, uint32_t k, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt,
-                                     hipStream_t s) {
+                                     const float *d_v, uint32_t k, uint32_t max_coords, uint32_t *d_ids, float *d_sc,
+                                     uint32_t *d_cnt, hipStream_t s) {
   LearnedFilter *f = filter;
   if (!f || !f->ready) return fail(SNN_E_INVALID, "search: no trained filter (call snn_filter_train first)");
   HIP_TRY(this, f->X.ensure((size_t)nq * kFeat * 4, s), "features");
@@ -373,6 +373,7 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
   lp.dim = cfg.dim;
   SearchOpts o;
   o.learned = &lp;
+  o.max_coords = max_coords;
   return run_search(nq, d_ptr, total, d_c, d_v, k, SNN_MODE_LEARNED, d_ids, d_sc, d_cnt, s, o);
 }
 

@@ -47,6 +47,7 @@ struct SearchWs {
   uint32_t *cand_cnt = nullptr, *queue = nullptr;
   uint64_t *cand = nullptr;
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
+  uint32_t *nz_full = nullptr;                  // [nq] whole non-zero count of each prepared query
   uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
   uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' merged candidates
   float *rr_sc = nullptr;
@@ -79,6 +80,7 @@ struct SearchOpts {
   const LearnedPass *learned = nullptr;  // filtered pass with a device-side plain fallback
   uint32_t rerank_k = 0;                 // > 0: the batch k is k' of Alg. 7 and this many are returned
   uint32_t hash_cap = 0;                 // re-rank: LDS hash slots per query
+  uint32_t max_coords = 0;               // anytime budget: coordinates scored per query (0 = all)
   const uint32_t *thr_init = nullptr;  // initial inclusive threshold keys (learned filter)
   const uint32_t *kq = nullptr;        // per-query k (<= the batch k)
   const uint32_t *keff = nullptr;      // count below which the filter check reports a fallback
@@ -120,7 +122,7 @@ struct GraphKey {
   bool persistent, prof;
   const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *qseq;
   const void *lX, *ly, *lthr, *lkeff, *lPb, *ltab;
-  uint32_t ldelta, lkeff_v, rerank_k, hash_cap;
+  uint32_t ldelta, lkeff_v, rerank_k, hash_cap, max_coords;
   const void *cslot, *rr, *fwd;
   uint64_t ebase;
   hipStream_t stream;
@@ -128,6 +130,7 @@ struct GraphKey {
     return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
            lX == o.lX && ly == o.ly && lthr == o.lthr && lkeff == o.lkeff && lPb == o.lPb && ltab == o.ltab &&
            ldelta == o.ldelta && lkeff_v == o.lkeff_v && rerank_k == o.rerank_k && hash_cap == o.hash_cap &&
+           max_coords == o.max_coords &&
            cslot == o.cslot && rr == o.rr && fwd == o.fwd &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&
@@ -252,8 +255,8 @@ struct snn_index {
                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s,
                         const snn::SearchOpts &o);
   snn_status search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
-                            const float *d_v, uint32_t k, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt,
-                            hipStream_t s);
+                            const float *d_v, uint32_t k, uint32_t max_coords, uint32_t *d_ids, float *d_sc,
+                            uint32_t *d_cnt, hipStream_t s);
   void tune_init();
   void release_extras();
 };
