@@ -22,18 +22,20 @@ __device__ __forceinline__ cptr<T> as_const(const T *p) {
 // it stops once a bin holds exactly the keys still needed (normally after the
 // three passes that fix the 32-bit score; ties at the k-th score go on into
 // the id bits). The keys at or above the found prefix are then exactly the k
-// best; only they are sorted (bitonic, at most 4,096 in LDS).
+// best. kSorted: only they are sorted (bitonic, at most 4,096 in LDS) and
+// written in order; otherwise (the k' candidates of the re-rank, up to 65,536)
+// they are written in the order found, with their slots.
 // ---------------------------------------------------------------------------
 constexpr int kSelBlock = 512;
 constexpr int kSelWaves = kSelBlock / 64;
 constexpr int kSelBins = 4096;
 
-template <bool kPay>
+template <bool kPay, bool kSorted>
 __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   __shared__ uint32_t hist[kSelBins];
   __shared__ uint32_t part[kSelBlock];
-  __shared__ uint64_t sel[kMaxK];
-  __shared__ uint32_t sels[kPay ? kMaxK : 1];
+  __shared__ uint64_t sel[kSorted ? kMaxK : 1];
+  __shared__ uint32_t sels[kPay && kSorted ? kMaxK : 1];
   __shared__ uint32_t sh_bin, sh_need, sh_pos;
   uint32_t q = a.q0 + blockIdx.y;
   if (a.qlist) {
@@ -43,14 +45,14 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const uint32_t G = a.groups_in;
   const uint32_t *cnts = a.in_cnt + (size_t)q * G;
-  const uint64_t *base = a.in + (size_t)q * G * a.kmax;
+  const uint64_t *base = a.in + (size_t)q * G * a.in_stride;
   const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
   const bool bad = a.status && a.status[q] != 0u;
   // every key of the query: wave w walks groups w, w + 8, ..., its lanes the group's keys
   auto for_each = [&](auto f) {
     for (uint32_t g = (uint32_t)wave; g < G; g += kSelWaves) {
       const uint32_t c = cnts[g];
-      const uint64_t *src = base + (size_t)g * a.kmax;
+      const uint64_t *src = base + (size_t)g * a.in_stride;
       for (uint32_t e = (uint32_t)lane; e < c; e += 64) f(src[e], g, e);
     }
   };
@@ -118,19 +120,35 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       }
     }
   }
-  // the keep best keys (with their slots), then sorted
+  // the keep best keys (with their slots)
   if (tid == 0) sh_pos = 0;
   __syncthreads();
+  uint32_t *ids = a.res_ids + (size_t)q * a.kmax;
+  float *sc = a.res_scores + (size_t)q * a.kmax;
   if (keep > 0) {
     for_each([&](uint64_t key, uint32_t g, uint32_t e) {
       if (key >= T) {
         const uint32_t pos = atomicAdd(&sh_pos, 1u);
-        sel[pos] = key;
-        if (kPay) sels[pos] = a.in_slot[((size_t)q * G + g) * a.kmax + e];
+        const uint32_t slot = kPay ? a.in_slot[((size_t)q * G + g) * a.in_stride + e] : 0u;
+        if (kSorted) {
+          sel[pos] = key;
+          if (kPay) sels[pos] = slot;
+        } else {
+          ids[pos] = 0xFFFFFFFFu - (uint32_t)key;
+          sc[pos] = key_value((uint32_t)(key >> 32));
+          if (kPay) a.res_slots[(size_t)q * a.kmax + pos] = slot;
+        }
       }
     });
   }
   __syncthreads();
+  if (!kSorted) {
+    if (tid == 0) {
+      a.res_cnt[q] = keep;
+      if (a.fallback) a.fallback[q] = (!bad && a.keff && M < a.keff[q]) ? 1u : 0u;
+    }
+    return;
+  }
   uint32_t np = 1;
   while (np < keep) np <<= 1;
   for (uint32_t i = keep + tid; i < np; i += kSelBlock) sel[i] = 0ull;
@@ -154,8 +172,6 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       }
     }
   __syncthreads();
-  uint32_t *ids = a.res_ids + (size_t)q * a.kmax;
-  float *sc = a.res_scores + (size_t)q * a.kmax;
   for (uint32_t r = tid; r < keep; r += kSelBlock) {
     const uint64_t key = sel[r];
     ids[r] = 0xFFFFFFFFu - (uint32_t)key;
@@ -168,12 +184,14 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   }
 }
 
-hipError_t launch_select(const SelectArgs &a, hipStream_t s) {
-  if (a.kmax == 0 || a.kmax > kMaxK || !a.res_ids || !a.res_scores || !a.res_cnt) return hipErrorInvalidValue;
+hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
+  if (a.kmax == 0 || a.in_stride == 0 || !a.res_ids || !a.res_scores || !a.res_cnt) return hipErrorInvalidValue;
+  if (sorted ? a.kmax > kMaxK : a.kmax > kMaxKPrime) return hipErrorInvalidValue;
   const bool pay = a.in_slot != nullptr;
-  if (pay && a.res_slots == nullptr) return hipErrorInvalidValue;
-  if (pay) hipLaunchKernelGGL(k_select<true>, dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else hipLaunchKernelGGL(k_select<false>, dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  if (pay != (a.res_slots != nullptr)) return hipErrorInvalidValue;
+  if (sorted && !pay) hipLaunchKernelGGL((k_select<false, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else if (!sorted && pay) hipLaunchKernelGGL((k_select<true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else return hipErrorInvalidValue;  // the two forms the search uses
   return hipGetLastError();
 }
 

@@ -1,19 +1,19 @@
-// Ranking with k' >= k (Alg. 7): the k' candidates of each query, chosen by
-// their Sinnamon scores, are fetched from the forward store and scored with
-// the exact inner product of Eq. 2; the k best by exact score are returned,
-// ties by the lower external id.
+// Ranking with k' >= k (Alg. 7), first half: the k' candidates of each query,
+// chosen by their Sinnamon scores, are fetched from the forward store and
+// scored with the exact inner product of Eq. 2. The k best by exact score
+// (ties by the lower external id) are then picked by the select kernel.
 //
-// One workgroup of 8 waves per query. The query's non-zeros go into an
-// open-addressing hash table in LDS (coordinate -> value), so a document
-// entry costs one LDS probe whatever the dimensionality. Each wave takes 64
-// candidates at a time: lane l fetches the slot, forward-store offset and
-// length of candidate l, then the wave walks the candidates one after
-// another, its 64 lanes reading 64 consecutive (coordinate, value) entries of
-// the document per step (coalesced 512-byte reads) and summing q_j * x_j in
-// FP32; a fixed butterfly of cross-lane adds finishes each sum, so the result
-// does not depend on timing. The exact scores become 64-bit keys
-// ord(score) << 32 | (0xFFFFFFFF - id) in LDS, sorted descending (bitonic),
-// and the first k are written out.
+// One workgroup of 8 waves per query. The query's non-zeros (all of them,
+// whatever the anytime budget of the scoring) go into an open-addressing hash
+// table in LDS (coordinate -> value), so a document entry costs one LDS probe
+// whatever the dimensionality. Each wave takes 64 candidates at a time: lane l
+// fetches the slot, forward-store offset and length of candidate l, then the
+// wave walks the candidates one after another, its 64 lanes reading 64
+// consecutive (coordinate, value) entries of the document per step
+// (coalesced 512-byte reads) and summing q_j * x_j in FP32; a fixed butterfly
+// of cross-lane adds finishes each sum, so the result does not depend on
+// timing. Each exact score leaves as a 64-bit key
+// ord(score) << 32 | (0xFFFFFFFF - id).
 #include <algorithm>
 
 #include "snn_device.h"
@@ -29,23 +29,17 @@ __device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
 }
 
 __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
-  extern __shared__ uint64_t lds[];
+  extern __shared__ uint32_t lds[];
   const uint32_t cap = a.hash_cap, mask = cap - 1u;
   const uint32_t shift = 32u - (uint32_t)__builtin_ctz(cap);
-  uint64_t *keys = lds;                                  // [pow2(kprime)]
-  uint32_t npow = 1;
-  while (npow < a.kprime) npow <<= 1;
-  uint32_t *hk = (uint32_t *)(lds + npow);               // [cap] coordinates
-  float *hv = (float *)(hk + cap);                       // [cap] values
+  uint32_t *hk = lds;                      // [cap] coordinates
+  float *hv = (float *)(lds + cap);        // [cap] values
   const uint32_t q = a.q0 + blockIdx.x;
   const uint32_t n = a.cand_cnt[q];
   const uint32_t ne = a.qd.status[q] ? 0u : a.nz_full[q];  // the exact score uses every coordinate
   const uint64_t e0 = a.qd.qptr[q] - a.qd.ebase;
   const int tid = threadIdx.x;
-  if (2u * ne > cap) {  // the launcher sizes the table for every query; never taken
-    if (tid == 0) a.out_cnt[q] = 0;
-    return;
-  }
+  if (2u * ne > cap) return;  // the launcher sizes the table for every query; never taken
 
   // the query as a hash table: linear probing, at most half full
   for (uint32_t i = tid; i < cap; i += kRrBlock) hk[i] = kEmpty;
@@ -101,57 +95,23 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
       for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
       if ((uint32_t)lane == t) {
         const float s = acc == 0.0f ? 0.0f : acc;  // -0 -> +0
-        keys[c] = ((uint64_t)ord_key(s) << 32) | (uint64_t)(0xFFFFFFFFu - id);
+        a.keys[cbase + c] = ((uint64_t)ord_key(s) << 32) | (uint64_t)(0xFFFFFFFFu - id);
       }
     }
   }
-  __syncthreads();
-
-  // the k best exact scores: bitonic sort of the keys, descending
-  uint32_t np = 1;
-  while (np < n) np <<= 1;
-  for (uint32_t i = n + tid; i < np; i += kRrBlock) keys[i] = 0ull;
-  for (uint32_t size = 2; size <= np; size <<= 1)
-    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (uint32_t i = tid; i < (np >> 1); i += kRrBlock) {
-        const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
-        const uint32_t hi = lo + stride;
-        const bool down = (lo & size) == 0;
-        const uint64_t x = keys[lo], y = keys[hi];
-        if ((x < y) == down) {
-          keys[lo] = y;
-          keys[hi] = x;
-        }
-      }
-    }
-  __syncthreads();
-  const uint32_t kk = min(a.k, n);
-  for (uint32_t r = tid; r < kk; r += kRrBlock) {
-    const uint64_t key = keys[r];
-    a.out_ids[(size_t)q * a.k + r] = 0xFFFFFFFFu - (uint32_t)key;
-    a.out_scores[(size_t)q * a.k + r] = key_value((uint32_t)(key >> 32));
-  }
-  if (tid == 0) a.out_cnt[q] = kk;
-}
-
-static size_t rerank_lds(const RerankArgs &a) {
-  size_t npow = 1;
-  while (npow < a.kprime) npow <<= 1;
-  return npow * 8 + (size_t)a.hash_cap * 8;
 }
 
 hipError_t rerank_init() {
-  // the largest table (8,192 slots) and candidate list (4,096 keys): 96 KB of LDS
-  return hipFuncSetAttribute((const void *)k_rerank, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  // the largest table: 8,192 slots, 64 KB of LDS
+  return hipFuncSetAttribute((const void *)k_rerank, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
 }
 
 hipError_t launch_rerank(const RerankArgs &a, uint32_t nq, hipStream_t s) {
   if (nq == 0) return hipSuccess;
-  if (a.kprime == 0 || a.kprime > kMaxK || a.k == 0 || a.k > a.kprime || a.hash_cap < 64 || a.hash_cap > 8192 ||
-      (a.hash_cap & (a.hash_cap - 1)) || !a.fw.ent)
+  if (a.kprime == 0 || a.kprime > kMaxKPrime || a.hash_cap < 64 || a.hash_cap > 8192 ||
+      (a.hash_cap & (a.hash_cap - 1)) || !a.fw.ent || !a.keys)
     return hipErrorInvalidValue;
-  const size_t lds = rerank_lds(a);
+  const size_t lds = (size_t)a.hash_cap * 8;
   for (uint32_t c0 = 0; c0 < nq; c0 += 65535u) {
     RerankArgs b = a;
     b.q0 = a.q0 + c0;

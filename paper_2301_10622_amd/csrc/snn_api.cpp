@@ -458,7 +458,8 @@ extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete
 
 // Device workspace for one batch: prepared entries, per-query state, tile
 // candidates. Laid out in one allocation.
-snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, bool slots,
+// kt: candidates a tile keeps per query; kprime > 0: the re-rank's buffers too.
+snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime,
                                         SearchWs &w, Workspace &W, hipStream_t stream) {
   const uint32_t h = cfg.h;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -478,7 +479,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   const size_t o_stats = o; o += al(32);
   const size_t o_nz = o; o += al((size_t)nq * 4);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
-  HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * k * 8 + 64, stream), "candidate buffer");
+  HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * kt * 8 + 64, stream), "candidate buffer");
   char *p = (char *)W.ws.p;
   w.cnt = (uint32_t *)(p + o_cnt);
   w.status = (uint32_t *)(p + o_status);
@@ -497,14 +498,18 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
   w.cand = (uint64_t *)W.cand.p;
   w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
-  if (slots) {
-    HIP_TRY(this, W.cslot.ensure((size_t)nq * tiles * k * 4 + 64, stream), "candidate slots");
-    HIP_TRY(this, W.rr.ensure((size_t)nq * k * 12 + (size_t)nq * 4 + 1024, stream), "re-rank candidates");
+  w.rk = nullptr;
+  if (kprime) {
+    const size_t kp = kprime;
+    HIP_TRY(this, W.cslot.ensure((size_t)nq * tiles * kt * 4 + 64, stream), "candidate slots");
+    const size_t o_keys = al((size_t)nq * kp * 12 + (size_t)nq * 4);
+    HIP_TRY(this, W.rr.ensure(o_keys + (size_t)nq * kp * 8 + 256, stream), "re-rank candidates");
     w.cslot = (uint32_t *)W.cslot.p;
     w.rr_ids = (uint32_t *)W.rr.p;
-    w.rr_sc = (float *)(w.rr_ids + (size_t)nq * k);
-    w.rr_slot = (uint32_t *)(w.rr_sc + (size_t)nq * k);
-    w.rr_cnt = w.rr_slot + (size_t)nq * k;
+    w.rr_sc = (float *)(w.rr_ids + (size_t)nq * kp);
+    w.rr_slot = (uint32_t *)(w.rr_sc + (size_t)nq * kp);
+    w.rr_cnt = w.rr_slot + (size_t)nq * kp;
+    w.rk = (uint64_t *)((char *)W.rr.p + o_keys);
   }
   return SNN_OK;
 }
@@ -512,12 +517,13 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t k,
 // Enqueue the selection of each query's top-k over all of its tile groups.
 snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStream_t s) {
   SelectArgs m{};
-  m.groups_in = j.tiles;
+  m.groups_in = j.in ? 1u : j.tiles;
+  m.in_stride = j.in_stride;
   m.kmax = j.k;
   m.kq = j.kq;
   m.keff = j.keff;
-  m.in = w.cand;
-  m.in_cnt = w.cand_cnt;
+  m.in = j.in ? j.in : w.cand;
+  m.in_cnt = j.in ? j.in_cnt : w.cand_cnt;
   m.status = w.status;
   m.qlist = j.qlist;
   m.nlist = j.nlist;
@@ -531,7 +537,7 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
   for (uint32_t c0 = 0; c0 < j.nqm; c0 += kMaxGridY) {
     m.q0 = j.q0 + c0;
     m.nq = std::min<uint32_t>(kMaxGridY, j.nqm - c0);
-    HIP_TRY(this, launch_select(m, s), "select kernel");
+    HIP_TRY(this, launch_select(m, j.sorted, s), "select kernel");
   }
   return SNN_OK;
 }
@@ -568,7 +574,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   a.qd = qd;
   a.nq = p.nq;
   a.tiles = p.tiles;
-  a.kmax = p.k;
+  a.kmax = p.kt;
   a.kq = o.kq;
   a.thr = w.thr;
   a.cand = w.cand;
@@ -584,6 +590,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   MergeJob mj;
   mj.tiles = p.tiles;
   mj.k = p.k;
+  mj.in_stride = p.kt;
   mj.kq = o.kq;
   mj.keff = keff;
   mj.res_ids = rerank ? w.rr_ids : p.d_ids;
@@ -591,6 +598,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   mj.res_cnt = rerank ? w.rr_cnt : p.d_cnt;
   mj.res_slots = rerank ? w.rr_slot : nullptr;
   mj.slots = rerank;
+  mj.sorted = !rerank;
   mj.emitted = w.stats;
   mj.set_fallback = true;
   if (p.mode == SNN_MODE_PLAIN) {
@@ -639,16 +647,26 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     r.fw = fw;
     r.qd = qd;
     r.kprime = p.k;
-    r.k = o.rerank_k;
     r.hash_cap = o.hash_cap;
     r.cand_ids = w.rr_ids;
     r.cand_slots = w.rr_slot;
     r.cand_cnt = w.rr_cnt;
     r.nz_full = w.nz_full;
-    r.out_ids = p.d_ids;
-    r.out_scores = p.d_sc;
-    r.out_cnt = p.d_cnt;
+    r.keys = w.rk;
     HIP_TRY(this, launch_rerank(r, p.nq, s), "re-rank kernel");
+    // the k best of the k' exact scores, in order
+    MergeJob fin;
+    fin.k = o.rerank_k;
+    fin.in = w.rk;
+    fin.in_cnt = w.rr_cnt;
+    fin.in_stride = p.k;
+    fin.res_ids = p.d_ids;
+    fin.res_scores = p.d_sc;
+    fin.res_cnt = p.d_cnt;
+    fin.q0 = 0;
+    fin.nqm = p.nq;
+    st = enqueue_merge(w, fin, s);
+    if (st != SNN_OK) return st;
   }
   if (!lp) return SNN_OK;
   // plain fallback of the learned filter, over the flagged queries only
@@ -685,7 +703,8 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   const uint32_t tile_docs = (uint32_t)kBlock * p.R;
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
-  return prepare_workspace(nq, total - o.ebase, k, p.tiles, o.rerank_k != 0, p.w, o.wsp ? *o.wsp : wsp, s);
+  p.kt = std::min<uint32_t>(k, tile_docs);
+  return prepare_workspace(nq, total - o.ebase, p.kt, p.tiles, o.rerank_k ? k : 0, p.w, o.wsp ? *o.wsp : wsp, s);
 }
 
 snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
@@ -778,7 +797,7 @@ static snn_status check_params(snn_index *ix, uint32_t k, const snn_search_param
   if (p.k_prime != 0) {
     if (p.k_prime < k) return ix->fail(SNN_E_INVALID, "re-rank: need k <= k' (k = %u, k' = %u)", k, p.k_prime);
     if (!ix->has_fwd) return ix->fail(SNN_E_INVALID, "re-rank: the index has no forward store (SNN_FORWARD_STORE)");
-    if (p.k_prime > kMaxK) return ix->fail(SNN_E_INVALID, "re-rank: k' must be <= %u", kMaxK);
+    if (p.k_prime > kMaxKPrime) return ix->fail(SNN_E_INVALID, "re-rank: k' must be <= %u", kMaxKPrime);
     if (p.mode != SNN_MODE_BATCHED) return ix->fail(SNN_E_INVALID, "re-rank: runs in SNN_MODE_BATCHED only");
   }
   return SNN_OK;

@@ -31,7 +31,8 @@ constexpr int kBlock = 64 * kWaves;      // threads per workgroup
 constexpr uint32_t kTileMax = 16384;     // largest tile (docs); capacity is a multiple
 constexpr int kMergeCap = 8192;          // candidates one merge workgroup sorts in LDS
 constexpr int kPrepCap = 4096;           // max non-zeros of one query
-constexpr uint32_t kMaxK = 4096;
+constexpr uint32_t kMaxK = 4096;        // largest k of a sorted result
+constexpr uint32_t kMaxKPrime = 65536;  // largest k' of the re-rank (Alg. 7)
 
 struct DevIndex {
   uint64_t *bits;
@@ -94,11 +95,12 @@ struct TileArgs {
 struct SelectArgs {
   uint32_t nq;
   uint32_t q0;
-  uint32_t groups_in;   // tile groups per query
-  uint32_t kmax;        // stride of a group and of a result row
+  uint32_t groups_in;   // candidate groups per query (tiles)
+  uint32_t in_stride;   // stride of a group
+  uint32_t kmax;        // k, and the stride of a result row
   const uint32_t *kq;   // per-query k (nullable)
   const uint32_t *keff; // per-query required count for the filter check (nullable)
-  const uint64_t *in;     // [nq][groups_in][kmax] keys
+  const uint64_t *in;     // [nq][groups_in][in_stride] keys
   const uint32_t *in_cnt; // [nq][groups_in]
   uint32_t *res_ids;    // [nq][kmax]
   float *res_scores;
@@ -141,22 +143,23 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
-// the final top-k of each query straight from all its tile groups (radix select)
-hipError_t launch_select(const SelectArgs &a, hipStream_t s);
-// Alg. 7 ranking of the merged k' candidates of each query.
+// the top-k of each query straight from all its candidate groups (radix select);
+// sorted: the k <= 4,096 results in key order (no slots); unsorted: the k' <=
+// 65,536 candidates of the re-rank in any order, with their slots
+hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s);
+// Alg. 7: exact scores of the selected k' candidates of each query, as keys
+// ord(score) << 32 | (0xFFFFFFFF - id); the k best are then selected.
 struct RerankArgs {
   DevForward fw;
   QueryDesc qd;
   uint32_t q0;              // first query of this launch
-  uint32_t kprime, k;
+  uint32_t kprime;          // stride of the candidate and key rows
   uint32_t hash_cap;        // LDS hash slots for the query (power of two > 2 * max nnz)
-  const uint32_t *cand_ids;   // [nq][kprime] from the final merge
+  const uint32_t *cand_ids;   // [nq][kprime]
   const uint32_t *cand_slots; // [nq][kprime]
   const uint32_t *cand_cnt;   // [nq]
   const uint32_t *nz_full;    // [nq] non-zeros of each prepared query (all of them, whatever the budget)
-  uint32_t *out_ids;        // [nq][k]
-  float *out_scores;
-  uint32_t *out_cnt;        // [nq]
+  uint64_t *keys;             // [nq][kprime] out: exact-score keys
 };
 hipError_t launch_rerank(const RerankArgs &a, uint32_t nq, hipStream_t s);
 hipError_t rerank_init();  // allows the re-rank kernel its largest LDS footprint

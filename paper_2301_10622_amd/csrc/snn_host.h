@@ -49,8 +49,9 @@ struct SearchWs {
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
   uint32_t *nz_full = nullptr;                  // [nq] whole non-zero count of each prepared query
   uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
-  uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' merged candidates
+  uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' selected candidates
   float *rr_sc = nullptr;
+  uint64_t *rk = nullptr;                       // re-rank: their exact-score keys
   unsigned long long *stats = nullptr;          // candidates emitted, selecting tiles (main, fallback pass)
 };
 
@@ -97,6 +98,11 @@ struct MergeJob {
   const uint32_t *kq = nullptr, *keff = nullptr;
   uint32_t *res_ids = nullptr, *res_cnt = nullptr, *res_slots = nullptr;
   bool slots = false;  // carry the candidates' slots (cslot) to the results
+  bool sorted = true;  // results in key order (k <= 4,096); else any order (re-rank candidates)
+  // input: the tile candidates (in == null) or one group per query
+  const uint64_t *in = nullptr;
+  const uint32_t *in_cnt = nullptr;
+  uint32_t in_stride = 0;
   float *res_scores = nullptr;
   const uint32_t *qlist = nullptr, *nlist = nullptr;
   unsigned long long *emitted = nullptr;
@@ -105,6 +111,7 @@ struct MergeJob {
 
 struct SearchPlan {
   uint32_t nq = 0, k = 0, tiles = 0, grid = 0;
+  uint32_t kt = 0;  // candidates one tile keeps per query: min(k, slots per tile)
   int mode = 0, R = 16;
   bool persistent = false;
   uint64_t total = 0;
@@ -244,7 +251,7 @@ struct snn_index {
                                const std::vector<float> &vals, size_t r0, size_t r1);
   snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
-  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t k, uint32_t tiles, bool slots,
+  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime,
                                snn::SearchWs &w, snn::Workspace &W, hipStream_t s);
   snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,

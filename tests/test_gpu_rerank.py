@@ -40,7 +40,8 @@ def small():
     return w, ix, ora
 
 
-@pytest.mark.parametrize("k,kp", [(10, 10), (10, 100), (10, 1000), (5, 4096), (100, 1000), (1, 7)])
+@pytest.mark.parametrize("k,kp", [(10, 10), (10, 100), (10, 1000), (5, 4096), (100, 1000), (1, 7), (10, 6000),
+                                  (1000, 20000)])
 def test_rerank_matches_oracle(small, k, kp):
     w, ix, ora = small
     ids, sc, cnt = ix.search_rerank(w.queries.indptr, w.queries.coords, w.queries.vals, k, kp)
@@ -138,6 +139,26 @@ def test_rerank_after_deletes_and_reinserts():
     assert full >= 0.85 * qs.rows
 
 
+def test_rerank_kprime_above_tile_and_collection():
+    """k' larger than a tile (4,096 slots) and than the collection: every tile
+    passes all its documents on, and with k' >= live the result is the exact
+    top-k, here k = 1,000 of 3,000 documents."""
+    P = _lib()
+    w = gen.make_small(2, docs=3000, queries=12)
+    ix = P.Index(w.n, w.m, w.h, capacity=3000, hash_seed=w.hash_seed, forward_store=True)
+    ix.set_schedule(16, 16, 2048, True)
+    P.load_docs(ix, w.docs)
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    q = w.queries
+    ids, sc, cnt = ix.search_rerank(q.indptr, q.coords, q.vals, 1000, 65536)
+    assert np.all(cnt == 1000)
+    for qi in range(q.rows):
+        ex, xa = ora.score_all(*q.row(qi), exact=True)
+        parity.check_query(ids[qi], sc[qi], ex, xa, {i: i for i in range(3000)}, np.arange(3000), 1000,
+                           what="exact q%d" % qi)
+    ix.close()
+
+
 def test_rerank_errors_and_empty_index():
     P = _lib()
     w = gen.make_small(0, docs=500, queries=5)
@@ -151,7 +172,7 @@ def test_rerank_errors_and_empty_index():
     ids, sc, cnt = fs.search_rerank(q.indptr, q.coords, q.vals, 10, 100)  # nothing inserted yet
     assert np.all(cnt == 0)
     P.load_docs(fs, w.docs)
-    for k, kp in ((10, 5), (0, 10), (10, 4097)):
+    for k, kp in ((10, 5), (0, 10), (10, 65537), (4097, 5000)):
         with pytest.raises(P.SnnError) as e:
             fs.search_rerank(q.indptr, q.coords, q.vals, k, kp)
         assert e.value.status == -1
