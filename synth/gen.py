@@ -250,6 +250,25 @@ def uneven_query_counts(rng, rows, lo=5, hi=400):
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), rows))).astype(np.int64)
 
 
+def bernoulli_counts(rng, rows, psi, n):
+    """nnz of vectors whose every coordinate is non-zero with probability psi / n."""
+    return rng.binomial(n, psi / n, rows).astype(np.int64)
+
+
+def make_gaussian(seed: int = 0, psi: int = 100, docs: int = 5_000_000, queries: int = 1000) -> Workload:
+    """The real-valued collections of Section 6.5: every coordinate is non-zero
+    with probability psi / n (uniform coordinates), values N(0, 1); 5M docs and
+    1,000 queries of the same law. G100: psi = 100, n = 10,000, 2m = 74;
+    G200: psi = 200, n = 32,000, 2m = 150 (Table 6); h = 1; k = 1,000."""
+    n, m = {100: (10_000, 37), 200: (32_000, 75)}[psi]
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    d = sparse_rows(seed, docs, n, 1.0, bernoulli_counts(rng, docs, psi, n), "normal", uniform_coords=True)
+    rngq = np.random.Generator(np.random.PCG64(seed + 2000))
+    q = sparse_rows(seed + 1, queries, n, 1.0, bernoulli_counts(rngq, queries, psi, n), "normal",
+                    uniform_coords=True)
+    return Workload("g%d-%dm-dim%d" % (psi, docs // 1_000_000, n), n, m, 1, seed, 1000, d, q, (1000,))
+
+
 def make_batch(seed: int = 0, docs: int = 4_000_000, queries: int = 8192) -> Workload:
     """Small-workload laws at 4M docs; 8,192 queries with nnz log-uniform 5..400; k=100."""
     n = 1000

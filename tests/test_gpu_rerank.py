@@ -180,3 +180,25 @@ def test_rerank_errors_and_empty_index():
     assert np.all(cnt == 10)
     plain.close()
     fs.close()
+
+
+def test_rerank_gaussian_law_k1000_kprime20000():
+    """The real-valued law of the paper's G100 collection (Section 6.5) at 200k
+    documents, with its k = 1,000 and k' = 20,000, full and anytime."""
+    P = _lib()
+    w = gen.make_gaussian(0, 100, docs=200_000, queries=6)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, forward_store=True)
+    P.load_docs(ix, w.docs)
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    q = w.queries
+    for c in (0, 30):
+        ids, sc, cnt = ix.search_ex(q.indptr, q.coords, q.vals, 1000, k_prime=20000, max_coords=c)
+        ids_of_pos = ora.ids.astype(np.int64)
+        for qi in range(q.rows):
+            qc, qv = q.row(qi)
+            est, ea = ora.score_all(qc, qv, max_coords=c)
+            ex, xa = ora.score_all(qc, qv, exact=True)
+            n = int(cnt[qi])
+            parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
+                                      what="g100-law c=%d q%d" % (c, qi))
+    ix.close()
