@@ -54,7 +54,11 @@ def lib():
         L.orc_pair_exact.restype = d
         L.orc_pair_exact.argtypes = [u32, P, P, u32, P, P]
         L.orc_build.restype = P
-        L.orc_build.argtypes = [u32, P, P, P, P, u32, u32, u32, u64]
+        L.orc_build.argtypes = [u32, P, P, P, P, u32, u32, u32, u64, u32]
+        L.orc_bf16_up.restype = d
+        L.orc_bf16_up.argtypes = [ctypes.c_float]
+        L.orc_bf16_down.restype = d
+        L.orc_bf16_down.argtypes = [ctypes.c_float]
         L.orc_free.argtypes = [P]
         L.orc_postings.restype = u64
         L.orc_postings.argtypes = [P]
@@ -143,7 +147,9 @@ def decode_doc(coords, vals, m: int, h: int, seed: int):
 class Index:
     """Coordinate-at-a-time oracle index over a fixed set of documents."""
 
-    def __init__(self, docs, n: int, m: int, h: int, seed: int, ids: Optional[np.ndarray] = None):
+    def __init__(self, docs, n: int, m: int, h: int, seed: int, ids: Optional[np.ndarray] = None,
+                 bf16: bool = False):
+        """bf16: the sketch is stored in bfloat16, U rounded up and L down."""
         self.indptr = np.ascontiguousarray(docs.indptr, dtype=np.int64)
         self.coords = _u32(docs.coords)
         self.vals = _f32(docs.vals)
@@ -151,7 +157,7 @@ class Index:
         self.ids = _u32(ids if ids is not None else np.arange(self.N))
         self.n, self.m, self.h, self.seed = n, m, h, seed
         self._h = lib().orc_build(self.N, _p(self.indptr), _p(self.coords), _p(self.vals), _p(self.ids),
-                                  n, m, h, seed)
+                                  n, m, h, seed, 1 if bf16 else 0)
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -196,6 +202,14 @@ class Index:
         lib().orc_rerank(self._h, nq, _p(qp), _p(qc), _p(qv), k, kprime, max_coords, threads, _p(ids), _p(sc), _p(ab),
                          _p(cnt))
         return ids[:, :k], sc[:, :k], ab[:, :k], cnt
+
+
+def bf16_up(x: float) -> float:
+    return float(lib().orc_bf16_up(float(x)))
+
+
+def bf16_down(x: float) -> float:
+    return float(lib().orc_bf16_down(float(x)))
 
 
 def max_threads() -> int:

@@ -17,6 +17,7 @@
  *   - sketching (Alg. 5): u[k] is the largest and l[k] the smallest value among
  *     the coordinates that at least one mapping sends to bucket k. A bucket no
  *     coordinate maps to is written as 0 (the paper is silent; it is never read).
+ *     Optionally stored in bfloat16 as the paper does, U rounded up, L down.
  *   - scoring (Alg. 6, T = infinity): the non-zero query coordinates sorted by
  *     |q_j| descending (ties: lower j first); for every document i on the
  *     inverted list of j add q_j * min_o U[pi_o(j)][i] if q_j > 0, else
@@ -108,6 +109,36 @@ void orc_sketch(uint32_t nnz, const uint32_t *coords, const float *vals, uint32_
   }
   if (filled) memcpy(filled, any, m);
   free(any);
+}
+
+/* bfloat16 keeps the top 16 bits of an IEEE binary32 value (sign, 8 exponent
+ * bits, 7 fraction bits). The paper stores its sketches in bfloat16 (Section
+ * 4.1). To keep every stored bound a bound, the upper half U is rounded toward
+ * +infinity and the lower half L toward -infinity: dropping the low 16 bits
+ * moves a value toward zero, so a positive value rounded up (a negative one
+ * rounded down) takes the next bfloat16 away from zero instead. */
+static float orc_bits_to_float(uint32_t b) {
+  float f;
+  memcpy(&f, &b, 4);
+  return f;
+}
+
+double orc_bf16_up(float x) {
+  uint32_t b;
+  memcpy(&b, &x, 4);
+  if ((b & 0xFFFFu) == 0) return (double)x;            /* already a bfloat16 */
+  uint32_t t = b & 0xFFFF0000u;                         /* toward zero */
+  if (x > 0.0f) t += 0x10000u;                          /* away from zero = up */
+  return (double)orc_bits_to_float(t);
+}
+
+double orc_bf16_down(float x) {
+  uint32_t b;
+  memcpy(&b, &x, 4);
+  if ((b & 0xFFFFu) == 0) return (double)x;
+  uint32_t t = b & 0xFFFF0000u;
+  if (x < 0.0f) t += 0x10000u;                          /* away from zero = down */
+  return (double)orc_bits_to_float(t);
 }
 
 /* Decoding used by Alg. 6: least upper bound and greatest lower bound of x[j]. */
@@ -240,8 +271,9 @@ typedef struct {
   float *vec_v;
 } orc_index;
 
+/* flags & 1: the sketch is stored in bfloat16, U rounded up and L down. */
 orc_index *orc_build(uint32_t N, const int64_t *indptr, const uint32_t *coords, const float *vals,
-                     const uint32_t *ids, uint32_t n, uint32_t m, uint32_t h, uint64_t seed) {
+                     const uint32_t *ids, uint32_t n, uint32_t m, uint32_t h, uint64_t seed, uint32_t flags) {
   orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
   ix->N = N;
   ix->n = n;
@@ -275,8 +307,9 @@ orc_index *orc_build(uint32_t N, const int64_t *indptr, const uint32_t *coords, 
     /* ... then write column i of U and L. */
     orc_sketch((uint32_t)(b - a), coords + a, vals + a, m, h, seed, u, l, NULL);
     for (uint32_t k = 0; k < m; ++k) {
-      ix->U[(size_t)k * N + i] = u[k];
-      ix->L[(size_t)k * N + i] = l[k];
+      /* u[k], l[k] are binary32 values (a max / min of the inputs) or 0 */
+      ix->U[(size_t)k * N + i] = (flags & 1u) ? orc_bf16_up((float)u[k]) : u[k];
+      ix->L[(size_t)k * N + i] = (flags & 1u) ? orc_bf16_down((float)l[k]) : l[k];
     }
   }
   free(u);

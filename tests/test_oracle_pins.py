@@ -366,6 +366,61 @@ def test_rerank_recall_never_drops_as_kprime_grows(small):
 
 
 # --------------------------------------------------------------------------
+# bfloat16 sketches (the paper's storage precision), U rounded up, L down
+# --------------------------------------------------------------------------
+
+def _all_bf16():
+    """Every finite bfloat16 value, from all 65,536 bit patterns, sorted."""
+    pats = (np.arange(65536, dtype=np.uint32) << 16).view(np.float32)
+    return np.unique(pats[np.isfinite(pats)].astype(np.float64))
+
+
+def test_bf16_rounding_is_the_nearest_bfloat16_above_and_below():
+    grid = _all_bf16()
+    rng = np.random.default_rng(11)
+    xs = np.concatenate([rng.standard_normal(3000), rng.exponential(1.0, 500) * 1e-30,
+                         rng.uniform(-1e30, 1e30, 500), grid[rng.integers(0, len(grid), 300)],
+                         [1.0, -1.0, 2.0 ** -126, 3.0e38]]).astype(np.float32)
+    for x in xs:
+        if x == 0:
+            continue
+        up, dn = O.bf16_up(x), O.bf16_down(x)
+        i = np.searchsorted(grid, float(x))  # first grid value >= x
+        assert up == grid[i], (x, up, grid[i])
+        j = np.searchsorted(grid, float(x), side="right") - 1  # last grid value <= x
+        assert dn == grid[j], (x, dn, grid[j])
+
+
+def test_bf16_sketch_keeps_theorem1_and_rounds_each_bound_outward():
+    """Estimates from a bfloat16 sketch are still never below the exact score
+    (any sign, h = 1 and 2), never below the float32-sketch estimate for
+    non-negative data, and equal to it when every value is a bfloat16."""
+    rng = np.random.default_rng(12)
+    for h, law in ((1, "normal"), (2, "normal"), (1, "exp")):
+        docs = gen.sparse_rows(90 + h, 500, 400, 1.1, rng.integers(10, 50, 500), law)
+        qs = gen.sparse_rows(95 + h, 8, 400, 1.1, np.full(8, 30), law)
+        b = O.Index(docs, 400, 16, h, 5, bf16=True)
+        f = O.Index(docs, 400, 16, h, 5)
+        for qi in range(qs.rows):
+            qc, qv = qs.row(qi)
+            sb, _ = b.score_all(qc, qv)
+            sf, _ = f.score_all(qc, qv)
+            ex, _ = f.score_all(qc, qv, exact=True)
+            assert np.all(sb >= ex - 1e-9)
+            if law == "exp":
+                assert np.all(sb >= sf - 1e-12) and np.any(sb > sf)
+    # values that are bfloat16 already: both sketches hold the same numbers
+    docs = gen.sparse_rows(97, 300, 200, 1.1, rng.integers(10, 40, 300), "normal")
+    docs.vals[:] = (docs.vals.view(np.uint32) & np.uint32(0xFFFF0000)).view(np.float32)
+    docs.vals[docs.vals == 0] = 1.0
+    qs = gen.sparse_rows(98, 4, 200, 1.1, np.full(4, 20), "normal")
+    b, f = O.Index(docs, 200, 16, 1, 6, bf16=True), O.Index(docs, 200, 16, 1, 6)
+    for qi in range(qs.rows):
+        qc, qv = qs.row(qi)
+        assert np.array_equal(b.score_all(qc, qv)[0], f.score_all(qc, qv)[0])
+
+
+# --------------------------------------------------------------------------
 # anytime scoring: a budget of c coordinates in the order of Alg. 6
 # --------------------------------------------------------------------------
 
