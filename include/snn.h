@@ -59,11 +59,19 @@ typedef enum {
  *             2014); the paper leaves the mappings unspecified
  *   capacity  maximum number of live documents (document slots); rounded up
  *             to a multiple of 16384 internally
- *   flags     0 or SNN_FORWARD_STORE */
+ *   flags     0 or an OR of SNN_FORWARD_STORE, SNN_SKETCH_BF16, SNN_UPPER_ONLY */
 /* Keep every live document's (coordinate, value) pairs on the device as well:
  * the vector storage S of Alg. 7, which the re-ranking search reads. Costs
  * 8 bytes per non-zero in HBM and the matching upload on insert. */
 #define SNN_FORWARD_STORE 1u
+/* Store the sketch in bfloat16, as the paper does (Section 4.1): U rounded
+ * toward +infinity and L toward -infinity, so every stored bound is still a
+ * bound (Theorem 1 holds) and the sketch takes half the bytes. */
+#define SNN_SKETCH_BF16 2u
+/* Keep only the upper half U (Sinnamon+ for non-negative collections): half
+ * the sketch memory; vectors and queries with a negative value are rejected
+ * (SNN_E_INVALID; in a device batch the query counts as malformed). */
+#define SNN_UPPER_ONLY 4u
 typedef struct {
   uint32_t dim;
   uint32_t m;
@@ -354,7 +362,8 @@ snn_status snn_serve_run(snn_index *ix, const snn_trace *trace, const snn_serve_
 
 /* Read back state for tests: the bucket table pi_o(j) as h x dim uint32
  * (row-major), and the stored sketch column (m floats each for U and L) of a
- * live id. Host pointers. */
+ * live id; bfloat16 sketches are widened exactly, and without an L half l
+ * gets zeros. Host pointers. */
 snn_status snn_bucket_table(snn_index *ix, uint32_t *out);
 snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l);
 

@@ -26,6 +26,8 @@ STATUS = {0: "SNN_OK", -1: "SNN_E_INVALID", -2: "SNN_E_EXISTS", -3: "SNN_E_NOT_F
           -5: "SNN_E_NOMEM", -6: "SNN_E_BUSY", -7: "SNN_E_DEVICE"}
 MODE_PLAIN, MODE_BATCHED, MODE_LEARNED = 0, 1, 2
 FORWARD_STORE = 1  # snn_config.flags: keep the vectors on the device (re-ranking, Alg. 7)
+SKETCH_BF16 = 2    # sketch stored in bfloat16, U rounded up and L down
+UPPER_ONLY = 4     # no L half (Sinnamon+, non-negative collections)
 
 # every symbol include/snn.h declares (checked by the test suite)
 EXPORTS = [
@@ -189,9 +191,11 @@ class Index:
     """A device-resident Sinnamon index (owns its device memory)."""
 
     def __init__(self, dim: int, m: int, h: int = 1, capacity: int = 1 << 16, hash_seed: int = 0, stream=None,
-                 forward_store: bool = False):
+                 forward_store: bool = False, sketch_bf16: bool = False, upper_only: bool = False):
         L = lib()
-        self._cfg = Config(dim, m, h, capacity, hash_seed, FORWARD_STORE if forward_store else 0, 0)
+        flags = (FORWARD_STORE if forward_store else 0) | (SKETCH_BF16 if sketch_bf16 else 0) | \
+            (UPPER_ONLY if upper_only else 0)
+        self._cfg = Config(dim, m, h, capacity, hash_seed, flags, 0)
         self.dim, self.m, self.h = dim, m, h
         h_ptr = ctypes.c_void_p()
         if stream is None and torch is not None and torch.cuda.is_available():

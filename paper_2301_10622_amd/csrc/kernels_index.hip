@@ -19,6 +19,16 @@ namespace snn {
 // ---------------------------------------------------------------------------
 constexpr int kInsertMaxM = 1024;
 
+// Directed rounding of a float32 to bfloat16 (its upper 16 bits): dropping the
+// low bits moves a value toward zero, so rounding up a positive value (down a
+// negative one) takes the next bfloat16 away from zero.
+__device__ __forceinline__ uint16_t bf16_round(float x, bool up) {
+  const uint32_t b = __builtin_bit_cast(uint32_t, x);
+  uint32_t t = b >> 16;
+  if ((b & 0xFFFFu) != 0u && ((x > 0.0f) == up)) t += 1u;
+  return (uint16_t)t;
+}
+
 __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const uint32_t *__restrict__ slots,
                                                const uint32_t *__restrict__ ids,
                                                const uint64_t *__restrict__ indptr,
@@ -53,10 +63,19 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
     atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + word], (unsigned long long)bit);
   }
   __syncthreads();
+  const bool bf = (ix.flags & kSketchBf16) != 0, lower = (ix.flags & kUpperOnly) == 0;
   for (uint32_t b = lane; b < m; b += 64) {
     const uint32_t a = umax[b], c = umin[b];
-    ix.U[(size_t)b * ix.cap + slot] = a ? key_value(a) : 0.0f;
-    ix.L[(size_t)b * ix.cap + slot] = (c != 0xFFFFFFFFu) ? key_value(c) : 0.0f;
+    const float u = a ? key_value(a) : 0.0f;
+    const float l = (c != 0xFFFFFFFFu) ? key_value(c) : 0.0f;
+    const size_t at = (size_t)b * ix.cap + slot;
+    if (bf) {
+      ((uint16_t *)ix.U)[at] = bf16_round(u, true);
+      if (lower) ((uint16_t *)ix.L)[at] = bf16_round(l, false);
+    } else {
+      ix.U[at] = u;
+      if (lower) ix.L[at] = l;
+    }
   }
   if (doc_off) {
     const uint64_t o = doc_off[d];
@@ -176,8 +195,8 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStre
 
 // ---------------------------------------------------------------------------
 // Query preparation (Alg. 6, first steps). One workgroup per query:
-//   drop zero values (nz), reject coordinates >= dim, non-finite values and
-//   duplicate coordinates, sort by |q_j| descending with ties to the lower j
+//   drop zero values (nz), reject coordinates >= dim, non-finite values,
+//   duplicate coordinates and, without an L half, negative values, sort by |q_j| descending with ties to the lower j
 //   (the order Alg. 6 walks the coordinates in), and look up the h buckets
 //   K = {pi_o(j)} of every coordinate. cnt[q], the number of coordinates the
 //   scoring walks, is cut to max_coords when that is smaller (the anytime
@@ -239,6 +258,7 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       const uint32_t vb = __builtin_bit_cast(uint32_t, vals[e0 + t]);
       const uint32_t ab = vb & 0x7FFFFFFFu;
       if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
+      if ((ix.flags & kUpperOnly) && ab != 0u && (vb >> 31)) atomicOr(&bad, 1u);  // no L to bound it
       if (ab != 0u) {
         atomicAdd(&nz, 1u);
         key = ((uint64_t)(~ab) << 32) | ((uint64_t)(j & 0x7FFFFFFFu) << 1) | (uint64_t)(vb >> 31);
@@ -278,6 +298,7 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       const uint32_t vb = __builtin_bit_cast(uint32_t, v);
       const uint32_t ab = vb & 0x7FFFFFFFu;
       if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
+      if ((ix.flags & kUpperOnly) && ab != 0u && (vb >> 31)) atomicOr(&bad, 1u);  // no L to bound it
       if (ab != 0u) {
         atomicAdd(&nz, 1u);
         key = ((uint64_t)(~ab) << 32) | ((uint64_t)(j & 0x7FFFFFFFu) << 1) | (uint64_t)(vb >> 31);

@@ -30,6 +30,42 @@ namespace snn {
 constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource, 32-bit data format
 constexpr int kOob = (int)0x80000000u;         // buffer offset past every range: load returns 0
 
+// Sketch rows hold float32 or, with SNN_SKETCH_BF16, bfloat16 values: a lane's
+// 4 slots of a 256-slot group are 16 or 8 consecutive bytes.
+template <bool kBf16>
+struct Elem {
+  static constexpr int kBytes = kBf16 ? 2 : 4;
+  static constexpr int kLane = 4 * kBytes;   // bytes per lane and group
+  static constexpr int kGroup = 64 * kLane;  // bytes per group
+};
+
+// The bounds of a lane's 4 slots in one group of a sketch row; 0 for an
+// out-of-range offset (no memory is touched then). A bfloat16 is the upper
+// half of a float32, so widening is a shift.
+template <bool kBf16>
+__device__ __forceinline__ void load4(__amdgpu_buffer_rsrc_t rs, int off, float (&v)[4]) {
+  if constexpr (kBf16) {
+    const uint32_t w0 = __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0);
+    const uint32_t w1 = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0);
+    v[0] = __builtin_bit_cast(float, w0 << 16);
+    v[1] = __builtin_bit_cast(float, w0 & 0xFFFF0000u);
+    v[2] = __builtin_bit_cast(float, w1 << 16);
+    v[3] = __builtin_bit_cast(float, w1 & 0xFFFF0000u);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, 0));
+  }
+}
+
+// Buffer resource over the wave's slots of row b of U (q_j > 0) or L.
+template <bool kBf16, int G>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const DevIndex &ix, bool upper, uint32_t b,
+                                                           uint32_t wslot0) {
+  const char *p = (const char *)(upper ? ix.U : ix.L) + ((size_t)b * ix.cap + wslot0) * Elem<kBf16>::kBytes;
+  return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, G * Elem<kBf16>::kGroup, kBufFlags);
+}
+
 // Read-only arrays are read through the constant address space: with a
 // wave-uniform address the loads become scalar loads (s_load), so bitmap words
 // and query entries land in SGPRs and drive the lane masks directly.
@@ -109,7 +145,7 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t wslot0, int x, int lane) {
   return wslot0 + 256u * (uint32_t)(x >> 2) + 4u * (uint32_t)lane + (uint32_t)(x & 3);
 }
 
-template <int R>
+template <int R, bool kBf16>
 __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
   constexpr int G = R / 4;  // 256-slot groups per wave
   const int lane = threadIdx.x & 63;
@@ -149,22 +185,18 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const uint32_t j = qj[e0 + c];
     const float qv = qq[e0 + c];
     const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
-    const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc<kBf16, G>(ix, qv > 0.0f, qb[e0 + c], wslot0);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
       const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
-      const int off = any ? r * 1024 + lane * 16 : kOob;
-      const float v0 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
-      const float v1 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4, 0, 0));
-      const float v2 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 8, 0, 0));
-      const float v3 = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off + 12, 0, 0));
-      acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v0, acc[4 * r + 0]);
-      acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v1, acc[4 * r + 1]);
-      acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v2, acc[4 * r + 2]);
-      acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v3, acc[4 * r + 3]);
+      const int off = any ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob;
+      float v[4];
+      load4<kBf16>(rs, off, v);
+      acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v[0], acc[4 * r + 0]);
+      acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v[1], acc[4 * r + 1]);
+      acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v[2], acc[4 * r + 2]);
+      acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v[3], acc[4 * r + 3]);
     }
   };
   // Two coordinates at a time: their scalar and vector loads are issued
@@ -175,22 +207,18 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const float qa = qq[e0 + c], qbv = qq[e0 + c + 1];
     const cptr<uint64_t> wa = bits + (size_t)ja * ix.W + wword0;
     const cptr<uint64_t> wb = bits + (size_t)jb * ix.W + wword0;
-    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)((qa > 0.0f ? ix.U : ix.L) + wslot0 + (size_t)qb[e0 + c] * cap), 0, G * 1024, kBufFlags);
-    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)((qbv > 0.0f ? ix.U : ix.L) + wslot0 + (size_t)qb[e0 + c + 1] * cap), 0, G * 1024, kBufFlags);
+    const __amdgpu_buffer_rsrc_t ra = row_rsrc<kBf16, G>(ix, qa > 0.0f, qb[e0 + c], wslot0);
+    const __amdgpu_buffer_rsrc_t rb = row_rsrc<kBf16, G>(ix, qbv > 0.0f, qb[e0 + c + 1], wslot0);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const uint64_t a0 = wa[4 * r], a1 = wa[4 * r + 1], a2 = wa[4 * r + 2], a3 = wa[4 * r + 3];
       const uint64_t b0 = wb[4 * r], b1 = wb[4 * r + 1], b2 = wb[4 * r + 2], b3 = wb[4 * r + 3];
-      const int offa = __builtin_amdgcn_inverse_ballot_w64(a0 | a1 | a2 | a3) ? r * 1024 + lane * 16 : kOob;
-      const int offb = __builtin_amdgcn_inverse_ballot_w64(b0 | b1 | b2 | b3) ? r * 1024 + lane * 16 : kOob;
+      const int lo = r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane;
+      const int offa = __builtin_amdgcn_inverse_ballot_w64(a0 | a1 | a2 | a3) ? lo : kOob;
+      const int offb = __builtin_amdgcn_inverse_ballot_w64(b0 | b1 | b2 | b3) ? lo : kOob;
       float va[4], vb[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        va[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, offa + 4 * i, 0, 0));
-        vb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, offb + 4 * i, 0, 0));
-      }
+      load4<kBf16>(ra, offa, va);
+      load4<kBf16>(rb, offb, vb);
       const uint64_t aw[4] = {a0, a1, a2, a3}, bw[4] = {b0, b1, b2, b3};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -208,7 +236,6 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
       const uint32_t j = qj[e0 + c];
       const float qv = qq[e0 + c];
       const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
-      const float *base = (qv > 0.0f ? ix.U : ix.L) + wslot0;
       // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows;
       // unused mappings repeat row 0, which leaves the min / max unchanged
       const bool upper = qv > 0.0f;
@@ -216,24 +243,21 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
 #pragma unroll
       for (int o = 0; o < 4; ++o) {
         const uint32_t oo = (uint32_t)o < h ? (uint32_t)o : 0u;
-        rs[o] = __builtin_amdgcn_make_buffer_rsrc((void *)(base + (size_t)qb[(e0 + c) * h + oo] * cap), 0, G * 1024,
-                                                  kBufFlags);
+        rs[o] = row_rsrc<kBf16, G>(ix, upper, qb[(e0 + c) * h + oo], wslot0);
       }
 #pragma unroll
       for (int r = 0; r < G; ++r) {
         const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
         const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
-        const int off = any ? r * 1024 + lane * 16 : kOob;
+        const int off = any ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob;
         float v[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) v[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[0], off + 4 * i, 0, 0));
+        load4<kBf16>(rs[0], off, v);
 #pragma unroll
         for (int o = 1; o < 4; ++o) {
+          float x[4];
+          load4<kBf16>(rs[o], off, x);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float x = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[o], off + 4 * i, 0, 0));
-            v[i] = upper ? __builtin_fminf(v[i], x) : __builtin_fmaxf(v[i], x);
-          }
+          for (int i = 0; i < 4; ++i) v[i] = upper ? __builtin_fminf(v[i], x[i]) : __builtin_fmaxf(v[i], x[i]);
         }
         acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v[0], acc[4 * r + 0]);
         acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v[1], acc[4 * r + 1]);
@@ -338,15 +362,26 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
-  __shared__ SelShared sh;
+template <int R, bool kBf16>
+__device__ __forceinline__ void one_item(const TileArgs &a, SelShared &sh) {
   uint32_t q = a.q0 + blockIdx.y;
   if (a.qlist) {
     if (q >= *as_const(a.nlist)) return;
     q = as_const(a.qlist)[q];
   }
-  tile_body<R>(a, q, blockIdx.x, sh);
+  tile_body<R, kBf16>(a, q, blockIdx.x, sh);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
+  __shared__ SelShared sh;
+  one_item<R, false>(a, sh);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles_bf16(TileArgs a) {
+  __shared__ SelShared sh;
+  one_item<R, true>(a, sh);
 }
 
 // Persistent form: a fixed grid pulls (query, tile) items from per-XCD queues.
@@ -355,9 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
 // the workgroups of one XCD work through one tile's bitmap and sketch slices
 // for many queries while those slices sit in that XCD's L2. A drained queue
 // steals from the others; every workgroup exits once all queues are drained.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
-  __shared__ SelShared sh;
+template <int R, bool kBf16>
+__device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &sh) {
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
@@ -373,27 +407,47 @@ __global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
       if (it >= items) break;
       const uint32_t t = x + X * (it / nq);
       const uint32_t q = a.qlist ? as_const(a.qlist)[it % nq] : it % nq;
-      tile_body<R>(a, q, t, sh);
+      tile_body<R, kBf16>(a, q, t, sh);
     }
   }
 }
 
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
+  __shared__ SelShared sh;
+  persistent_items<R, false>(a, sh);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_tiles_persistent_bf16(TileArgs a) {
+  __shared__ SelShared sh;
+  persistent_items<R, true>(a, sh);
+}
+
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s) {
   dim3 grid(a.tiles, nq_launch);
+  const bool bf = (a.ix.flags & kSketchBf16) != 0;
   switch (R) {
-    case 16: hipLaunchKernelGGL(k_tiles<16>, grid, dim3(kBlock), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_tiles<32>, grid, dim3(kBlock), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_tiles<64>, grid, dim3(kBlock), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(bf ? k_tiles_bf16<16> : k_tiles<16>, grid, dim3(kBlock), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(bf ? k_tiles_bf16<32> : k_tiles<32>, grid, dim3(kBlock), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(bf ? k_tiles_bf16<64> : k_tiles<64>, grid, dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s) {
+  const bool bf = (a.ix.flags & kSketchBf16) != 0;
   switch (R) {
-    case 16: hipLaunchKernelGGL(k_tiles_persistent<16>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_tiles_persistent<32>, dim3(grid), dim3(kBlock), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_tiles_persistent<64>, dim3(grid), dim3(kBlock), 0, s, a); break;
+    case 16:
+      hipLaunchKernelGGL(bf ? k_tiles_persistent_bf16<16> : k_tiles_persistent<16>, dim3(grid), dim3(kBlock), 0, s, a);
+      break;
+    case 32:
+      hipLaunchKernelGGL(bf ? k_tiles_persistent_bf16<32> : k_tiles_persistent<32>, dim3(grid), dim3(kBlock), 0, s, a);
+      break;
+    case 64:
+      hipLaunchKernelGGL(bf ? k_tiles_persistent_bf16<64> : k_tiles_persistent<64>, dim3(grid), dim3(kBlock), 0, s, a);
+      break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -122,6 +122,10 @@ bool snn_check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const floa
       ix->fail(SNN_E_INVALID, "%s: non-finite value at coordinate %u", what, c[t]);
       return false;
     }
+    if ((ix->cfg.flags & SNN_UPPER_ONLY) && v[t] < 0.0f) {
+      ix->fail(SNN_E_INVALID, "%s: negative value at coordinate %u (the index keeps no lower bounds)", what, c[t]);
+      return false;
+    }
     scratch.push_back(c[t]);
   }
   std::sort(scratch.begin(), scratch.end());
@@ -145,7 +149,8 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   if (!out) return SNN_E_INVALID;
   *out = nullptr;
   if (!cfg || cfg->dim == 0 || cfg->m == 0 || cfg->h == 0 || cfg->h > 4 || cfg->capacity == 0 ||
-      cfg->capacity > (1u << 31) || (cfg->flags & ~SNN_FORWARD_STORE) != 0 || cfg->dim >= (1u << 31))
+      cfg->capacity > (1u << 31) || (cfg->flags & ~(SNN_FORWARD_STORE | SNN_SKETCH_BF16 | SNN_UPPER_ONLY)) != 0 ||
+      cfg->dim >= (1u << 31))
     return SNN_E_INVALID;
   snn_index *ix = new (std::nothrow) snn_index();
   if (!ix) return SNN_E_NOMEM;
@@ -159,11 +164,13 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   d.h = cfg->h;
   d.cap = ix->cap;
   d.W = ix->W;
+  d.flags = (cfg->flags & SNN_SKETCH_BF16 ? kSketchBf16 : 0u) | (cfg->flags & SNN_UPPER_ONLY ? kUpperOnly : 0u);
+  const bool lower = (cfg->flags & SNN_UPPER_ONLY) == 0;
   size_t bits_bytes = (size_t)cfg->dim * ix->W * 8;
-  size_t sk_bytes = (size_t)cfg->m * ix->cap * 4;
+  size_t sk_bytes = (size_t)cfg->m * ix->cap * (cfg->flags & SNN_SKETCH_BF16 ? 2 : 4);
   hipError_t e = hipSuccess;
   if ((e = hipMalloc(&d.bits, bits_bytes)) != hipSuccess || (e = hipMalloc(&d.live, (size_t)ix->W * 8)) != hipSuccess ||
-      (e = hipMalloc(&d.U, sk_bytes)) != hipSuccess || (e = hipMalloc(&d.L, sk_bytes)) != hipSuccess ||
+      (e = hipMalloc(&d.U, sk_bytes)) != hipSuccess || (lower && (e = hipMalloc(&d.L, sk_bytes)) != hipSuccess) ||
       (e = hipMalloc(&d.slot2id, (size_t)ix->cap * 4)) != hipSuccess ||
       (e = hipMalloc(&d.bucket, (size_t)cfg->h * cfg->dim * 4)) != hipSuccess) {
     snn_status st = e == hipErrorOutOfMemory ? SNN_E_NOMEM : SNN_E_DEVICE;
@@ -174,7 +181,7 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   if (hipMemsetAsync(d.bits, 0, bits_bytes, ix->stream) != hipSuccess ||
       hipMemsetAsync(d.live, 0, (size_t)ix->W * 8, ix->stream) != hipSuccess ||
       hipMemsetAsync(d.U, 0, sk_bytes, ix->stream) != hipSuccess ||
-      hipMemsetAsync(d.L, 0, sk_bytes, ix->stream) != hipSuccess ||
+      (lower && hipMemsetAsync(d.L, 0, sk_bytes, ix->stream) != hipSuccess) ||
       launch_fill_u32(d.slot2id, 0xFFFFFFFFu, ix->cap, ix->stream) != hipSuccess) {
     snn_destroy(ix);
     return SNN_E_DEVICE;
@@ -992,8 +999,27 @@ extern "C" snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, floa
   if (it == ix->id2slot.end()) return ix->fail(SNN_E_NOT_FOUND, "read_sketch: id %u is not live", id);
   const uint32_t s = it->second;
   HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
-  HIP_TRY(ix, hipMemcpy2D(u, 4, ix->dev.U + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "U readback");
-  HIP_TRY(ix, hipMemcpy2D(l, 4, ix->dev.L + s, (size_t)ix->cap * 4, 4, ix->cfg.m, hipMemcpyDeviceToHost), "L readback");
+  const uint32_t m = ix->cfg.m;
+  if (ix->cfg.flags & SNN_SKETCH_BF16) {
+    std::vector<uint16_t> hu(m, 0), hl(m, 0);
+    HIP_TRY(ix, hipMemcpy2D(hu.data(), 2, (uint16_t *)ix->dev.U + s, (size_t)ix->cap * 2, 2, m, hipMemcpyDeviceToHost),
+            "U readback");
+    if (ix->dev.L)
+      HIP_TRY(ix,
+              hipMemcpy2D(hl.data(), 2, (uint16_t *)ix->dev.L + s, (size_t)ix->cap * 2, 2, m, hipMemcpyDeviceToHost),
+              "L readback");
+    for (uint32_t b = 0; b < m; ++b) {
+      const uint32_t ub = (uint32_t)hu[b] << 16, lb = (uint32_t)hl[b] << 16;
+      memcpy(&u[b], &ub, 4);
+      memcpy(&l[b], &lb, 4);
+    }
+    return SNN_OK;
+  }
+  HIP_TRY(ix, hipMemcpy2D(u, 4, ix->dev.U + s, (size_t)ix->cap * 4, 4, m, hipMemcpyDeviceToHost), "U readback");
+  if (ix->dev.L)
+    HIP_TRY(ix, hipMemcpy2D(l, 4, ix->dev.L + s, (size_t)ix->cap * 4, 4, m, hipMemcpyDeviceToHost), "L readback");
+  else
+    for (uint32_t b = 0; b < m; ++b) l[b] = 0.0f;
   return SNN_OK;
 }
 

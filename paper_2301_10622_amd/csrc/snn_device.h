@@ -7,7 +7,9 @@
 //                                 stored as a bitmap over slots; W = cap / 64)
 //   live     uint64 [W]           bit s set when slot s holds a live document
 //   U, L     float  [m][cap]      the sketch matrix halves, one contiguous row per
-//                                 bucket (the transposed layout of Section 4.1)
+//                                 bucket (the transposed layout of Section 4.1);
+//                                 bfloat16 with SNN_SKETCH_BF16, no L with
+//                                 SNN_UPPER_ONLY
 //   slot2id  uint32 [cap]         external id of the document in each slot
 //   bucket   uint32 [h][dim]      the random mappings pi_o(j)
 //   fwd      uint2  [entries]     forward store (optional, DevForward): (coordinate,
@@ -42,7 +44,10 @@ struct DevIndex {
   uint32_t *slot2id;
   uint32_t *bucket;
   uint32_t dim, m, h, cap, W;
+  uint32_t flags;     // kSketchBf16 | kUpperOnly
 };
+constexpr uint32_t kSketchBf16 = 2u;  // U and L rows hold bfloat16 (U rounded up, L down)
+constexpr uint32_t kUpperOnly = 4u;   // no L half: non-negative collections (Sinnamon+)
 
 // Forward store (optional), kept out of DevIndex: the scoring kernel's
 // argument block stays small, which keeps its register use (and occupancy)
