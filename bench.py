@@ -52,6 +52,8 @@ def main():
     ap.add_argument("--kprimes", default="10,100,300,500,1000,4096",
                     help="k' values of the re-ranking (Alg. 7) forms on the 1M-doc index; empty to skip")
     ap.add_argument("--no-g100", action="store_true", help="skip the G100 workload of the paper (Section 6.5)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the bfloat16 / upper-only sketch variants of the 1M-doc index")
     ap.add_argument("--g200", action="store_true", help="also run the G200 workload (20 GB of bitmaps)")
     ap.add_argument("--anytime", default="5,10,20",
                     help="coordinate budgets of the anytime re-ranking forms (k' = 1000); empty to skip")
@@ -203,6 +205,37 @@ def main():
         log("rerank   k=%d k'=%-5d coords %-4s %8.3f ms/step  %10.0f q/s" % (args.k, kp, c or "all", ms,
                                                                           nq / (ms / 1000.0)))
 
+    # memory levers: the same collection with a bfloat16 and / or upper-only sketch
+    variants_res = {}
+    if not args.no_variants:
+        ix.close()
+        torch.cuda.empty_cache()
+        for vname, bf, up in (("bf16", True, False), ("upper_only", False, True), ("bf16_upper_only", True, True)):
+            vx = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
+                         forward_store=True, sketch_bf16=bf, upper_only=up)
+            P.load_docs(vx, w.docs)
+            vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]))
+            r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2)}
+            for form, kw in (("batched_k10", dict(k_prime=0, max_coords=0)),
+                             ("rerank_k1000_coords10", dict(k_prime=1000, max_coords=10))):
+                out = (torch.empty((nq, args.k), dtype=torch.int32, device=dev),
+                       torch.empty((nq, args.k), dtype=torch.float32, device=dev),
+                       torch.empty(nq, dtype=torch.int32, device=dev))
+                for _ in range(args.warmup):
+                    vx.search_ex_dev(ip, qc, qv, args.k, out=out, total=total, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    vx.search_ex_dev(ip, qc, qv, args.k, out=out, total=total, **kw)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+                r[form] = {"qps": nq / (ms / 1000.0), "ms_per_step": ms}
+                outs[("variant", vname, form)] = out
+                log("variant %-16s %-22s %8.3f ms/step  %10.0f q/s" % (vname, form, ms, nq / (ms / 1000.0)))
+            variants_res[vname] = r
+            vx.close()
+            torch.cuda.empty_cache()
+
     # the headline form: the fastest at the headline k
     cand = {n: forms["%s_k%d" % (n, args.k)] for n in args.forms.split(",")}
     best = max(cand, key=lambda n: cand[n]["qps"])
@@ -261,6 +294,13 @@ def main():
             rec.append(len(g & set(eids[i][: ecnt[i]].tolist())) / max(1, min(args.k, ecnt[i])))
             agree.append(len(g & set(oids[i][: ocnt[i]].tolist())) / max(1, ocnt[i]))
         result["recall_at_%d" % args.k] = round(float(np.mean(rec)), 4)
+        for vname, r in variants_res.items():
+            for form in ("batched_k10", "rerank_k1000_coords10"):
+                g_ids = outs[("variant", vname, form)][0][:S].cpu().numpy().astype(np.int64)
+                g_cnt = outs[("variant", vname, form)][2][:S].cpu().numpy()
+                rr = [len(set(g_ids[i][: g_cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist()))
+                      / max(1, min(args.k, ecnt[i])) for i in range(S)]
+                r[form]["recall_at_%d" % args.k] = round(float(np.mean(rr)), 4)
         # re-ranked forms: recall against exact brute force, agreement with the oracle's Alg. 7
         for kp, c in variants:
             rids, _, _, rcnt = ora.rerank(sample, args.k, kp, threads=threads, max_coords=c)
@@ -281,6 +321,10 @@ def main():
                                   "exact_brute_force_qps": round(S / t_exact, 2)}
         log("oracle: %.2f q/s (estimate), %.2f q/s (exact); recall@%d %.4f" % (
             S / t_est, S / t_exact, args.k, result["recall_at_%d" % args.k]))
+    if variants_res:
+        result["sketch_variants"] = {v: {f: ({kk: (round(x, 4) if isinstance(x, float) else x) for kk, x in d.items()}
+                                             if isinstance(d, dict) else d) for f, d in r.items()}
+                                     for v, r in variants_res.items()}
     if rerank:
         result["rerank"] = {("k'=%d" % kp) + ("" if not c else " coords=%d" % c):
                             {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
@@ -291,7 +335,8 @@ def main():
             result["at_recall_0.9"] = {"form": "rerank", "k_prime": kp, "max_coords": c,
                                        "qps": round(rerank[(kp, c)]["qps"], 1),
                                        "recall_at_%d" % args.k: rerank[(kp, c)]["recall_at_%d" % args.k]}
-    ix.close()
+    if args.no_variants:
+        ix.close()
     if not args.no_small:
         result["learned_small"] = small_learned(args, dev, P, gen, np, torch)
     if not args.no_batch4m:
