@@ -214,7 +214,8 @@ def main():
             vx = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
                          forward_store=True, sketch_bf16=bf, upper_only=up)
             P.load_docs(vx, w.docs)
-            vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]))
+            vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]),
+                            sched["qgroup"])
             r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2)}
             for form, kw in (("batched_k10", dict(k_prime=0, max_coords=0)),
                              ("rerank_k1000_coords10", dict(k_prime=1000, max_coords=10))):
@@ -244,8 +245,7 @@ def main():
     per_launch_queries = nq / head["tile_launches_per_step"]
     ab_launch = alg_bytes(args.k) * per_launch_queries / nq
     achieved = ab_launch / (launch_ms / 1000.0) / 1e9
-    kname = ("k_tiles_persistent<%d>" if best != "plain" else "k_tiles<%d>") % (
-        sched["R_batch"] if best != "plain" else sched["R_plain"])
+    kname = tile_kernel_name(sched, best)
     traffic = measured_traffic(kname, args.k)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
@@ -348,6 +348,18 @@ def main():
     if not args.no_serving:
         result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def tile_kernel_name(sched, form):
+    """The scoring kernel a form launches under a schedule, as the profiler names
+    it (template arguments: slots per lane, bfloat16 sketch, queries per group)."""
+    if form == "plain":
+        return "k_tiles<%d>" % sched["R_plain"]
+    R, Q = sched["R_batch"], sched["qgroup"]
+    if Q > 1:
+        return ("k_tiles_persistent_grouped<%d, false, %d>" if sched["persistent"] else
+                "k_tiles_grouped<%d, false, %d>") % (R, Q)
+    return ("k_tiles_persistent<%d>" if sched["persistent"] else "k_tiles<%d>") % R
 
 
 def measured_traffic(kernel, k):

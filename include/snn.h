@@ -224,7 +224,12 @@ snn_status snn_last_batch_work(snn_index *ix, snn_batch_work *out);
 /* Launch schedule of the search kernels. R is the number of slots each lane
  * scores (a workgroup of 256 lanes covers a tile of 256 * R slots); grid is the
  * workgroup count of the persistent batched kernel; persistent = 0 launches one
- * workgroup per (query, tile) instead. */
+ * workgroup per (query, tile) instead. qgroup > 1 (h = 1 only) makes each
+ * batched workgroup score qgroup queries on its tile at once, loading each
+ * sketch row once for all of them; results are the same bits either way.
+ * Valid combinations: qgroup 1 with R_batch 16, 32, 64; qgroup 2 with
+ * R_batch 8 or 16; qgroup 3 with R_batch 16; qgroup 4 with R_batch 8.
+ * R_plain is 16, 32 or 64. */
 typedef struct {
   int32_t R_plain;
   int32_t R_batch;
@@ -233,10 +238,12 @@ typedef struct {
   float best_ms;      /* tuned batched pass, ms (0 if not tuned) */
   float default_ms;   /* same batch with the default schedule, ms */
   uint32_t tried;     /* candidate schedules timed */
+  uint32_t qgroup;    /* queries per batched workgroup (1 to 4) */
 } snn_schedule;
 
-/* Autotuner: time the candidate schedules (R in {16, 32, 64}; persistent grids
- * of 1024, 2048 and 4096 workgroups or one workgroup per item) on the given
+/* Autotuner: time the candidate schedules (R in {16, 32, 64} with qgroup 1,
+ * and (R, qgroup) in {(16, 2), (16, 3), (8, 4)} when h = 1; persistent grids of
+ * 1024, 2048 and 4096 workgroups or one workgroup per item) on the given
  * device-resident batch, keep the fastest for later searches of this index,
  * and report it in *out (may be NULL). Same arguments as snn_search_batch_dev
  * without the mode; scratch outputs are allocated internally. Blocking. */

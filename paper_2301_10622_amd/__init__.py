@@ -52,7 +52,7 @@ class SnnError(RuntimeError):
 class Schedule(ctypes.Structure):
     _fields_ = [("R_plain", ctypes.c_int32), ("R_batch", ctypes.c_int32), ("grid", ctypes.c_uint32),
                 ("persistent", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("default_ms", ctypes.c_float),
-                ("tried", ctypes.c_uint32)]
+                ("tried", ctypes.c_uint32), ("qgroup", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -393,8 +393,8 @@ class Index:
         self._check(lib().snn_get_schedule(self._h, ctypes.byref(sch)))
         return sch.as_dict()
 
-    def set_schedule(self, R_plain=16, R_batch=16, grid=2048, persistent=True):
-        sch = Schedule(R_plain, R_batch, grid, 1 if persistent else 0, 0.0, 0.0, 0)
+    def set_schedule(self, R_plain=16, R_batch=16, grid=2048, persistent=True, qgroup=1):
+        sch = Schedule(R_plain, R_batch, grid, 1 if persistent else 0, 0.0, 0.0, 0, qgroup)
         self._check(lib().snn_set_schedule(self._h, ctypes.byref(sch)))
 
     # ------------------------------------------------------------- learned filter

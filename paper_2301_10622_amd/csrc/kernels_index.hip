@@ -202,6 +202,14 @@ hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStre
 //   scoring walks, is cut to max_coords when that is smaller (the anytime
 //   budget; every entry is still written), and nz_full[q] (nullable) gets the
 //   whole count for the exact re-rank.
+//   With h = 1 the cnt scored entries are then stored by sketch row (bucket,
+//   then sign: U before L), ties in the order above. That is the order in
+//   which every search form adds a query's terms, so a kernel that walks
+//   several queries' entries row by row, loading each row once for all of
+//   them, adds each document's terms in the same order as one query alone,
+//   and every form gives bit-identical scores. At T = infinity the order of
+//   the additions changes rounding only; which coordinates are scored is
+//   still decided by the Alg. 6 order.
 // Sort keys are 64-bit: high word ~|q|bits (ascending = |q| descending), low
 // word (j << 1) | sign, so equal magnitudes fall back to the lower coordinate.
 // ---------------------------------------------------------------------------
@@ -247,15 +255,16 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
   }
   const int len = (int)len64;
   if (len <= 256) {
-    // short queries: rank counting instead of sorting (one barrier). Keys of
-    // distinct coordinates are distinct; equal coordinates are duplicates.
+    // short queries: rank counting instead of sorting. Keys of distinct
+    // coordinates are distinct; equal coordinates are duplicates.
     __shared__ uint32_t sj[256];
+    __shared__ uint64_t okey[256];
     const int t = threadIdx.x;
     uint64_t key = ~0ull;
-    uint32_t j = 0xFFFFFFFFu;
+    uint32_t j = 0xFFFFFFFFu, vb = 0;
     if (t < len) {
       j = coords[e0 + t];
-      const uint32_t vb = __builtin_bit_cast(uint32_t, vals[e0 + t]);
+      vb = __builtin_bit_cast(uint32_t, vals[e0 + t]);
       const uint32_t ab = vb & 0x7FFFFFFFu;
       if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
       if ((ix.flags & kUpperOnly) && ab != 0u && (vb >> 31)) atomicOr(&bad, 1u);  // no L to bound it
@@ -274,12 +283,25 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
         rank += keys[x] < key ? 1u : 0u;
       }
     }
-    __syncthreads();  // `bad` is final
+    __syncthreads();  // `bad` and `nz` are final
+    // scoring order: with h = 1 the scored entries by (row, rank), the rest after in rank order
+    const uint32_t scored = min(nz, max_coords);
+    uint64_t ok = ~0ull;
     if (t < len && !bad && key != ~0ull) {
-      const uint64_t e = e0 - qd.ebase + rank;
+      const uint32_t row = ix.h == 1 && rank < scored ? (ix.bucket[j] << 1) | (vb >> 31) : 0x7FFFFFFFu;
+      ok = ((uint64_t)row << 32) | rank;
+    }
+    if (t < len) okey[t] = ok;
+    __syncthreads();
+    if (t < len && !bad && key != ~0ull) {
+      uint32_t pos = 0;
+      for (int x = 0; x < len; ++x) pos += okey[x] < ok ? 1u : 0u;
+      const uint64_t e = e0 - qd.ebase + pos;
       qd.j[e] = j;
       qd.q[e] = vals[e0 + t];
-      for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+      if (ix.h == 1) qd.b[e] = (ix.bucket[j] << 1) | (vb >> 31);  // the sketch row: bucket, then U / L
+      else
+        for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
     }
     if (t == 0) {
       qd.cnt[q] = bad ? 0u : min(nz, max_coords);
@@ -338,16 +360,31 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
   }
   bitonic_sort_u64_asc(keys, n);
   const uint32_t cnt = nz;
-  for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-    const uint64_t k = keys[i];
+  // scoring order (see above): sort (row, rank) of the scored entries, h = 1
+  __shared__ uint64_t okeys[kPrepCap];
+  const uint32_t scored = min(cnt, max_coords);
+  for (uint32_t i = threadIdx.x; i < (uint32_t)n; i += blockDim.x) {
+    uint64_t ok = ~0ull;
+    if (i < cnt) {
+      const uint32_t lo = (uint32_t)keys[i];
+      const uint32_t row = ix.h == 1 && i < scored ? (ix.bucket[lo >> 1] << 1) | (lo & 1u) : 0x7FFFFFFFu;
+      ok = ((uint64_t)row << 32) | i;
+    }
+    okeys[i] = ok;
+  }
+  bitonic_sort_u64_asc(okeys, n);
+  for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
+    const uint64_t k = keys[(uint32_t)okeys[p]];
     const uint32_t ab = ~(uint32_t)(k >> 32);
     const uint32_t lo = (uint32_t)k;
     const uint32_t j = lo >> 1;
     const uint32_t vb = ab | ((lo & 1u) << 31);
-    const uint64_t e = e0 - qd.ebase + i;
+    const uint64_t e = e0 - qd.ebase + p;
     qd.j[e] = j;
     qd.q[e] = __builtin_bit_cast(float, vb);
-    for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+    if (ix.h == 1) qd.b[e] = (ix.bucket[j] << 1) | (vb >> 31);  // the sketch row: bucket, then U / L
+    else
+      for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
   }
   if (threadIdx.x == 0) {
     qd.cnt[q] = min(cnt, max_coords);

@@ -145,6 +145,9 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t wslot0, int x, int lane) {
   return wslot0 + 256u * (uint32_t)(x >> 2) + 4u * (uint32_t)lane + (uint32_t)(x & 3);
 }
 
+template <int R>
+__device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&acc)[R], SelShared &sh);
+
 template <int R, bool kBf16>
 __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
   constexpr int G = R / 4;  // 256-slot groups per wave
@@ -153,12 +156,9 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
   const uint32_t wword0 = wslot0 >> 6;
   const DevIndex &ix = a.ix;
-  const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
-  uint32_t *ccnt = a.cand_cnt + (size_t)q * a.tiles + t;
-  uint64_t *cout = a.cand + ((size_t)q * a.tiles + t) * a.kmax;
 
   if (as_const(a.qd.status)[q] != 0u) {  // malformed query: no candidates
-    if (threadIdx.x == 0) *ccnt = 0;
+    if (threadIdx.x == 0) a.cand_cnt[(size_t)q * a.tiles + t] = 0;
     return;
   }
 
@@ -185,7 +185,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const uint32_t j = qj[e0 + c];
     const float qv = qq[e0 + c];
     const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc<kBf16, G>(ix, qv > 0.0f, qb[e0 + c], wslot0);
+    const __amdgpu_buffer_rsrc_t rs = row_rsrc<kBf16, G>(ix, qv > 0.0f, qb[e0 + c] >> 1, wslot0);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
@@ -207,8 +207,8 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     const float qa = qq[e0 + c], qbv = qq[e0 + c + 1];
     const cptr<uint64_t> wa = bits + (size_t)ja * ix.W + wword0;
     const cptr<uint64_t> wb = bits + (size_t)jb * ix.W + wword0;
-    const __amdgpu_buffer_rsrc_t ra = row_rsrc<kBf16, G>(ix, qa > 0.0f, qb[e0 + c], wslot0);
-    const __amdgpu_buffer_rsrc_t rb = row_rsrc<kBf16, G>(ix, qbv > 0.0f, qb[e0 + c + 1], wslot0);
+    const __amdgpu_buffer_rsrc_t ra = row_rsrc<kBf16, G>(ix, qa > 0.0f, qb[e0 + c] >> 1, wslot0);
+    const __amdgpu_buffer_rsrc_t rb = row_rsrc<kBf16, G>(ix, qbv > 0.0f, qb[e0 + c + 1] >> 1, wslot0);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
       const uint64_t a0 = wa[4 * r], a1 = wa[4 * r + 1], a2 = wa[4 * r + 2], a3 = wa[4 * r + 3];
@@ -267,6 +267,20 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     }
   }
 
+  finish<R>(a, q, t, acc, sh);
+}
+
+// Selection and emission of one (query, tile) item from its scores.
+template <int R>
+__device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&acc)[R], SelShared &sh) {
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 64u * R;
+  const uint32_t wword0 = wslot0 >> 6;
+  const DevIndex &ix = a.ix;
+  const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
+  uint32_t *ccnt = a.cand_cnt + (size_t)q * a.tiles + t;
+  uint64_t *cout = a.cand + ((size_t)q * a.tiles + t) * a.kmax;
   // ---------------- selection keys ----------------
   uint32_t key[R];
   const cptr<uint64_t> lw = as_const(ix.live) + wword0;
@@ -362,6 +376,104 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   }
 }
 
+// Q queries on one tile (h = 1). Each query's scored entries are stored by
+// sketch row (k_prep), so the workgroup walks the Q lists together, row by
+// row: a row of U (or L) is loaded once for every query that has a coordinate
+// in it, and each query adds its terms in its own stored order, the order one
+// query alone uses. Scores of the Q queries stay in registers; each then goes
+// through the same selection as a single query.
+template <int R, bool kBf16, int Q>
+__device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t nq_eff, SelShared &sh) {
+  constexpr int G = R / 4;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
+  const uint32_t wword0 = wslot0 >> 6;
+  const DevIndex &ix = a.ix;
+  const cptr<uint32_t> qj = as_const(a.qd.j);
+  const cptr<float> qq = as_const(a.qd.q);
+  const cptr<uint32_t> qb = as_const(a.qd.b);
+  const cptr<uint64_t> bits = as_const(ix.bits);
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  // per query: the cursor into its list, the list's end and the sketch row of
+  // the entry under the cursor (none past the end)
+  uint32_t qid[Q], row[Q];
+  uint64_t cur[Q], end[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const uint32_t slot = grp * (uint32_t)Q + (uint32_t)i;
+    qid[i] = kNone;
+    cur[i] = end[i] = 0;
+    if (slot < nq_eff) {
+      const uint32_t q = a.qlist ? as_const(a.qlist)[slot] : slot;
+      qid[i] = q;
+      if (as_const(a.qd.status)[q] == 0u) {
+        cur[i] = as_const(a.qd.qptr)[q] - a.qd.ebase;
+        end[i] = cur[i] + as_const(a.qd.cnt)[q];
+      }
+    }
+    row[i] = cur[i] < end[i] ? qb[cur[i]] : kNone;
+  }
+  float acc[Q][R];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+#pragma unroll
+    for (int x = 0; x < R; ++x) acc[i][x] = 0.0f;
+  for (;;) {
+    uint32_t rmin = kNone;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) rmin = min(rmin, row[i]);
+    if (rmin == kNone) break;
+    // the row's bounds for the wave's slots, read densely: one 16-byte (8-byte)
+    // load per lane and group
+    const char *rp = (const char *)((rmin & 1u) == 0u ? ix.U : ix.L) +
+                     ((size_t)(rmin >> 1) * ix.cap + wslot0) * Elem<kBf16>::kBytes;
+    float v[G][4];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      if constexpr (kBf16) {
+        const uint2 x = ((const uint2 *)rp)[r * 64 + lane];
+        v[r][0] = __builtin_bit_cast(float, x.x << 16);
+        v[r][1] = __builtin_bit_cast(float, x.x & 0xFFFF0000u);
+        v[r][2] = __builtin_bit_cast(float, x.y << 16);
+        v[r][3] = __builtin_bit_cast(float, x.y & 0xFFFF0000u);
+      } else {
+        const float4 x = ((const float4 *)rp)[r * 64 + lane];
+        v[r][0] = x.x;
+        v[r][1] = x.y;
+        v[r][2] = x.z;
+        v[r][3] = x.w;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      while (row[i] == rmin) {
+        const cptr<uint64_t> wp = bits + (size_t)qj[cur[i]] * ix.W + wword0;
+        const float qv = qq[cur[i]];
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          const uint64_t w[4] = {wp[4 * r], wp[4 * r + 1], wp[4 * r + 2], wp[4 * r + 3]};
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            acc[i][4 * r + k] =
+                __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w[k]) ? qv : 0.0f, v[r][k], acc[i][4 * r + k]);
+        }
+        ++cur[i];
+        row[i] = cur[i] < end[i] ? qb[cur[i]] : kNone;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (qid[i] == kNone) continue;
+    if (as_const(a.qd.status)[qid[i]] != 0u) {  // malformed query: no candidates
+      if (threadIdx.x == 0) a.cand_cnt[(size_t)qid[i] * a.tiles + t] = 0;
+      continue;
+    }
+    finish<R>(a, qid[i], t, acc[i], sh);
+  }
+}
+
 template <int R, bool kBf16>
 __device__ __forceinline__ void one_item(const TileArgs &a, SelShared &sh) {
   uint32_t q = a.q0 + blockIdx.y;
@@ -422,6 +534,63 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles_persistent_bf16(TileArgs a) {
   __shared__ SelShared sh;
   persistent_items<R, true>(a, sh);
+}
+
+// Grouped forms: items are (query group, tile); group g holds the queries
+// g * Q .. g * Q + Q - 1 of the batch (or of the query list).
+template <int R, bool kBf16, int Q>
+__global__ __launch_bounds__(kBlock) void k_tiles_grouped(TileArgs a) {
+  __shared__ SelShared sh;
+  const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
+  const uint32_t grp = a.q0 + blockIdx.y;
+  if (grp * (uint32_t)Q >= nq) return;
+  tile_group<R, kBf16, Q>(a, grp, blockIdx.x, nq, sh);
+}
+
+template <int R, bool kBf16, int Q>
+__global__ __launch_bounds__(kBlock) void k_tiles_persistent_grouped(TileArgs a) {
+  __shared__ SelShared sh;
+  const uint32_t X = a.xcds;
+  const uint32_t home = blockIdx.x % X;
+  const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
+  const uint32_t ng = (nq + Q - 1) / Q;
+  for (uint32_t step = 0; step < X; ++step) {
+    const uint32_t x = (home + step) % X;
+    const uint32_t tiles_x = a.tiles > x ? (a.tiles - x + X - 1) / X : 0u;
+    const uint32_t items = tiles_x * ng;
+    for (;;) {
+      __syncthreads();
+      if (threadIdx.x == 0) sh.item = atomicAdd(&a.queue[x], 1u);
+      __syncthreads();
+      const uint32_t it = sh.item;
+      if (it >= items) break;
+      tile_group<R, kBf16, Q>(a, it % ng, x + X * (it / ng), nq, sh);
+    }
+  }
+}
+
+template <int R, int Q>
+static void launch_grouped_rq(const TileArgs &a, bool bf, bool persistent, uint32_t grid, uint32_t ng_launch,
+                              hipStream_t s) {
+  if (persistent) {
+    if (bf) hipLaunchKernelGGL((k_tiles_persistent_grouped<R, true, Q>), dim3(grid), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_tiles_persistent_grouped<R, false, Q>), dim3(grid), dim3(kBlock), 0, s, a);
+  } else {
+    if (bf) hipLaunchKernelGGL((k_tiles_grouped<R, true, Q>), dim3(a.tiles, ng_launch), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_tiles_grouped<R, false, Q>), dim3(a.tiles, ng_launch), dim3(kBlock), 0, s, a);
+  }
+}
+
+hipError_t launch_tiles_grouped(const TileArgs &a, int R, int Q, bool persistent, uint32_t grid, uint32_t ng_launch,
+                                hipStream_t s) {
+  if (a.ix.h != 1) return hipErrorInvalidValue;
+  const bool bf = (a.ix.flags & kSketchBf16) != 0;
+  if (R == 16 && Q == 2) launch_grouped_rq<16, 2>(a, bf, persistent, grid, ng_launch, s);
+  else if (R == 16 && Q == 3) launch_grouped_rq<16, 3>(a, bf, persistent, grid, ng_launch, s);
+  else if (R == 8 && Q == 2) launch_grouped_rq<8, 2>(a, bf, persistent, grid, ng_launch, s);
+  else if (R == 8 && Q == 4) launch_grouped_rq<8, 4>(a, bf, persistent, grid, ng_launch, s);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s) {

@@ -632,7 +632,19 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     a.q0 = 0;
     if (p.persistent) HIP_TRY(this, launch_fill_u32(w.queue, 0u, 64, s), "queue fill");
     if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
-    if (p.persistent) {
+    if (p.qgroup > 1) {
+      // several queries per workgroup; the non-persistent grid covers query groups
+      const uint32_t ng = (p.nq + p.qgroup - 1) / p.qgroup;
+      if (p.persistent) {
+        HIP_TRY(this, launch_tiles_grouped(a, p.R, p.qgroup, true, p.grid, 0, s), "grouped tile kernel");
+      } else {
+        for (uint32_t c0 = 0; c0 < ng; c0 += kMaxGridY) {
+          a.q0 = c0;
+          HIP_TRY(this, launch_tiles_grouped(a, p.R, p.qgroup, false, 0, std::min<uint32_t>(kMaxGridY, ng - c0), s),
+                  "grouped tile kernel");
+        }
+      }
+    } else if (p.persistent) {
       HIP_TRY(this, launch_tiles_persistent(a, p.R, p.grid, s), "persistent tile kernel");
     } else {
       for (uint32_t c0 = 0; c0 < p.nq; c0 += kMaxGridY) {
@@ -705,6 +717,8 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   p.d_sc = d_sc;
   p.d_cnt = d_cnt;
   p.R = mode == SNN_MODE_PLAIN ? tune.R_plain : tune.R_batch;
+  p.qgroup = mode == SNN_MODE_PLAIN || cfg.h != 1 ? 1 : tune.qgroup;
+  if (p.qgroup == 1 && p.R < 16) p.R = 16;  // the one-query kernels are built for R >= 16
   p.persistent = mode != SNN_MODE_PLAIN && tune.persistent;
   p.grid = tune.grid;
   const uint32_t tile_docs = (uint32_t)kBlock * p.R;
@@ -744,6 +758,7 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   // batched forms replay a captured HIP graph of the whole pass
   GraphKey key{};
   key.nq = nq; key.total = total; key.k = k; key.mode = mode; key.R = p.R; key.grid = p.grid;
+  key.qgroup = (uint32_t)p.qgroup;
   key.persistent = p.persistent; key.tiles = p.tiles; key.prof = false;
   key.ptr = d_ptr; key.c = d_c; key.v = d_v; key.ids = d_ids; key.sc = d_sc; key.cnt = d_cnt;
   key.thr = o.thr_init; key.kq = o.kq; key.keff = o.keff; key.stream = s;

@@ -66,7 +66,8 @@ struct QueryDesc {
   uint32_t *status;      // [nq] 0 = ok, else malformed
   uint32_t *j;           // [total]
   float *q;              // [total]
-  uint32_t *b;           // [total * h]
+  uint32_t *b;           // [total * h] the buckets pi_o(j); with h = 1 the sketch row
+                         // (pi_0(j) << 1) | (q_j < 0), i.e. the bucket and the U / L half
   uint64_t ebase;        // qptr value of the first entry held in j, q, b
 };
 
@@ -148,6 +149,10 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s)
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
+// h = 1: Q queries per workgroup, one sketch-row load for all of them; the
+// non-persistent form launches (tiles, ng_launch) groups from group a.q0
+hipError_t launch_tiles_grouped(const TileArgs &a, int R, int Q, bool persistent, uint32_t grid, uint32_t ng_launch,
+                                hipStream_t s);
 // the top-k of each query straight from all its candidate groups (radix select);
 // sorted: the k <= 4,096 results in key order (no slots); unsorted: the k' <=
 // 65,536 candidates of the re-rank in any order, with their slots

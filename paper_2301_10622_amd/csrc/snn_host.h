@@ -61,6 +61,7 @@ struct Tune {
   int R_batch = 16;      // same, batched mode
   bool persistent = true;
   uint32_t grid = 2048;  // persistent grid
+  int qgroup = 1;        // queries per batched workgroup (h = 1)
 };
 
 struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
@@ -112,7 +113,7 @@ struct MergeJob {
 struct SearchPlan {
   uint32_t nq = 0, k = 0, tiles = 0, grid = 0;
   uint32_t kt = 0;  // candidates one tile keeps per query: min(k, slots per tile)
-  int mode = 0, R = 16;
+  int mode = 0, R = 16, qgroup = 1;
   bool persistent = false;
   uint64_t total = 0;
   const uint64_t *d_ptr = nullptr;
@@ -124,7 +125,7 @@ struct SearchPlan {
 };
 
 struct GraphKey {
-  uint32_t nq, k, mode, R, grid, tiles;
+  uint32_t nq, k, mode, R, grid, tiles, qgroup;
   uint64_t total;
   bool persistent, prof;
   const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *qseq;
@@ -135,6 +136,7 @@ struct GraphKey {
   hipStream_t stream;
   bool operator==(const GraphKey &o) const {
     return nq == o.nq && k == o.k && mode == o.mode && R == o.R && grid == o.grid && tiles == o.tiles &&
+           qgroup == o.qgroup &&
            lX == o.lX && ly == o.ly && lthr == o.lthr && lkeff == o.lkeff && lPb == o.lPb && ltab == o.ltab &&
            ldelta == o.ldelta && lkeff_v == o.lkeff_v && rerank_k == o.rerank_k && hash_cap == o.hash_cap &&
            max_coords == o.max_coords &&

@@ -15,6 +15,7 @@ struct Cand {
   int R;
   bool persistent;
   uint32_t grid;
+  int qgroup;
 };
 
 }  // namespace
@@ -28,17 +29,25 @@ extern "C" snn_status snn_get_schedule(snn_index *ix, snn_schedule *out) {
   out->best_ms = ix->tune_best_ms;
   out->default_ms = ix->tune_default_ms;
   out->tried = ix->tune_tried;
+  out->qgroup = (uint32_t)ix->tune.qgroup;
   return SNN_OK;
 }
 
 static bool valid_R(int R) { return R == 16 || R == 32 || R == 64; }
 
+// the (R, qgroup) pairs the batched kernels are built for
+static bool valid_batch(int R, uint32_t Q) {
+  return (Q == 1 && valid_R(R)) || (Q == 2 && (R == 8 || R == 16)) || (Q == 3 && R == 16) || (Q == 4 && R == 8);
+}
+
 extern "C" snn_status snn_set_schedule(snn_index *ix, const snn_schedule *in) {
   if (!ix || !in) return SNN_E_INVALID;
-  if (!valid_R(in->R_plain) || !valid_R(in->R_batch) || in->grid == 0 || in->grid > (1u << 20))
-    return ix->fail(SNN_E_INVALID, "schedule: R must be 16, 32 or 64 and grid in 1..2^20");
+  if (!valid_R(in->R_plain) || !valid_batch(in->R_batch, in->qgroup) || in->grid == 0 || in->grid > (1u << 20) ||
+      (in->qgroup > 1 && ix->cfg.h != 1))
+    return ix->fail(SNN_E_INVALID, "schedule: invalid (R_batch, qgroup) or grid (qgroup > 1 needs h = 1)");
   ix->tune.R_plain = in->R_plain;
   ix->tune.R_batch = in->R_batch;
+  ix->tune.qgroup = (int)in->qgroup;
   ix->tune.grid = in->grid;
   ix->tune.persistent = in->persistent != 0;
   return SNN_OK;
@@ -89,16 +98,22 @@ extern "C" snn_status snn_autotune(snn_index *ix, uint32_t nq, const uint64_t *i
   ix->prof_on = false;
   std::vector<Cand> cands;
   for (int R : {16, 32, 64}) {
-    for (uint32_t g : {1024u, 2048u, 4096u}) cands.push_back({R, true, g});
-    cands.push_back({R, false, 0u});
+    for (uint32_t g : {1024u, 2048u, 4096u}) cands.push_back({R, true, g, 1});
+    cands.push_back({R, false, 0u, 1});
   }
+  if (ix->cfg.h == 1)
+    for (auto rq : {std::make_pair(16, 2), std::make_pair(16, 3), std::make_pair(8, 4)}) {
+      for (uint32_t g : {2048u, 4096u}) cands.push_back({rq.first, true, g, rq.second});
+      cands.push_back({rq.first, false, 0u, rq.second});
+    }
   float def_ms = 0, best_ms = 1e30f;
-  Cand best = {saved.R_batch, saved.persistent, saved.grid};
+  Cand best = {saved.R_batch, saved.persistent, saved.grid, saved.qgroup};
   snn_status st = time_pass(ix, nq, indptr, total, coords, vals, k, ids, sc, cnt, s, 2, def_ms);
   uint32_t tried = 0;
   for (const Cand &c : cands) {
     if (st != SNN_OK) break;
     ix->tune.R_batch = c.R;
+    ix->tune.qgroup = c.qgroup;
     ix->tune.persistent = c.persistent;
     ix->tune.grid = c.persistent ? c.grid : saved.grid;
     float ms = 0;
@@ -106,7 +121,7 @@ extern "C" snn_status snn_autotune(snn_index *ix, uint32_t nq, const uint64_t *i
     ++tried;
     if (st == SNN_OK && ms < best_ms) {
       best_ms = ms;
-      best = {c.R, c.persistent, c.persistent ? c.grid : saved.grid};
+      best = {c.R, c.persistent, c.persistent ? c.grid : saved.grid, c.qgroup};
     }
   }
   // plain (one query at a time): the tile size sets how many workgroups one query fills
@@ -143,6 +158,7 @@ extern "C" snn_status snn_autotune(snn_index *ix, uint32_t nq, const uint64_t *i
     return st;
   }
   ix->tune.R_batch = best.R;
+  ix->tune.qgroup = best.qgroup;
   ix->tune.persistent = best.persistent;
   ix->tune.grid = best.grid;
   ix->tune.R_plain = best_plain_R;

@@ -256,17 +256,21 @@ def test_all_schedules_give_identical_results(small):
     w, ix, ora = small
     t = _dev_batch(w.queries)
     ref = _dev_search(ix, t, 10, P.MODE_PLAIN)
+    ref100 = _dev_search(ix, t, 100, P.MODE_PLAIN)
     saved = ix.schedule()
     try:
-        for R in (16, 32, 64):
+        for R, Q in ((16, 1), (32, 1), (64, 1), (16, 2), (16, 3), (8, 2), (8, 4)):
             for persistent, grid in ((True, 1024), (True, 4096), (False, 2048)):
-                ix.set_schedule(R_plain=R, R_batch=R, grid=grid, persistent=persistent)
+                ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=grid, persistent=persistent, qgroup=Q)
                 for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
-                    got = _dev_search(ix, t, 10, mode)
-                    for a, b in zip(ref, got):
-                        assert np.array_equal(a, b), (R, persistent, grid, mode)
+                    for k in (10, 100):
+                        got = _dev_search(ix, t, k, mode)
+                        want = ref if k == 10 else ref100
+                        for a, b in zip(want, got):
+                            assert np.array_equal(a, b), (R, Q, persistent, grid, mode, k)
     finally:
-        ix.set_schedule(saved["R_plain"], saved["R_batch"], saved["grid"], bool(saved["persistent"]))
+        ix.set_schedule(saved["R_plain"], saved["R_batch"], saved["grid"], bool(saved["persistent"]),
+                        saved["qgroup"])
 
 
 def test_graph_replays_match_eager_between_mutations():
@@ -304,7 +308,8 @@ def test_autotune_keeps_results_and_reports_schedule(small):
     t = _dev_batch(w.queries)
     before = _dev_search(ix, t, 10, P.MODE_BATCHED)
     sch = ix.autotune(*t, 10)
-    assert sch["R_batch"] in (16, 32, 64) and sch["R_plain"] in (16, 32, 64) and sch["tried"] == 15
+    assert (sch["R_batch"], sch["qgroup"]) in ((16, 1), (32, 1), (64, 1), (16, 2), (16, 3), (8, 4))
+    assert sch["R_plain"] in (16, 32, 64) and sch["tried"] == 24
     assert sch["best_ms"] > 0 and sch["best_ms"] <= sch["default_ms"] * 1.5
     after = _dev_search(ix, t, 10, P.MODE_BATCHED)
     for a, b in zip(before, after):
