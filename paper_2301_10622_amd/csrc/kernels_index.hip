@@ -48,8 +48,8 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
   __syncthreads();
   const uint64_t e0 = indptr[d], e1 = indptr[d + 1];
   const uint32_t slot = slots[d];
-  const uint64_t bit = 1ull << slot_bit(slot);
-  const size_t word = slot_word(slot);
+  const uint64_t pbit = 1ull << post_bit(slot);
+  const size_t pword = post_word(slot);
   for (uint64_t e = e0 + lane; e < e1; e += 64) {
     const uint32_t j = coords[e];
     const float v = vals[e];
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
       atomicMax(&umax[b], key);
       atomicMin(&umin[b], key);
     }
-    atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + word], (unsigned long long)bit);
+    atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + pword], (unsigned long long)pbit);
   }
   __syncthreads();
   const bool bf = (ix.flags & kSketchBf16) != 0, lower = (ix.flags & kUpperOnly) == 0;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
   }
   if (lane == 0) {
     ix.slot2id[slot] = ids[d];
-    atomicOr((unsigned long long *)&ix.live[word], (unsigned long long)bit);
+    atomicOr((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)(1ull << slot_bit(slot)));
   }
 }
 
@@ -113,12 +113,13 @@ __global__ __launch_bounds__(64) void k_delete(DevIndex ix, uint32_t n, const ui
   const uint32_t d = blockIdx.x;
   if (d >= n) return;
   const uint32_t slot = slots[d];
-  const uint64_t mask = ~(1ull << slot_bit(slot));
-  const size_t word = slot_word(slot);
+  const uint64_t pmask = ~(1ull << post_bit(slot));
+  const size_t pword = post_word(slot);
   if (clear_bits)
     for (uint64_t e = indptr[d] + threadIdx.x; e < indptr[d + 1]; e += 64)
-      atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + word], (unsigned long long)mask);
-  if (clear_live && threadIdx.x == 0) atomicAnd((unsigned long long *)&ix.live[word], (unsigned long long)mask);
+      atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + pword], (unsigned long long)pmask);
+  if (clear_live && threadIdx.x == 0)
+    atomicAnd((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)~(1ull << slot_bit(slot)));
 }
 
 hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,

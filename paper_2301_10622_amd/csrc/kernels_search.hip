@@ -4,16 +4,17 @@
 //
 // A workgroup owns one (query, doc tile) pair. The tile is 256 * R consecutive
 // slots, R / 4 groups of 256 per wave; in a group lane l owns the 4 adjacent
-// slots 4l .. 4l+3. For each query coordinate j, in the order of Alg. 6, the
-// wave reads the 4 posting-bitmap words of each of its groups; word i holds
-// bit l for slot 4l + i, so each word is directly a wavefront lane mask
-// (inverse ballot). A lane with any of its 4 slots on the list reads their 4
-// bounds from sketch row pi(j) -- min over the U rows if q_j > 0, max over the
-// L rows otherwise -- with one 16-byte load, and adds q_j * bound for the
-// slots whose bit is set. A lane with none loads from an out-of-range buffer
-// offset, which returns 0 without touching memory, so the inner loop has no
-// branches and one vector memory instruction serves 256 slots. Scores never
-// leave registers.
+// slots 4l .. 4l+3. For each query coordinate j, in the order of Alg. 6, each
+// lane reads its own posting bits of j -- the posting bitmaps are lane-major,
+// so that is one 2-byte load per lane and 1,024-slot block, and the bits of
+// several coordinates are fetched together to share one memory latency. A lane
+// with any of its 4 slots on the list reads their 4 bounds from sketch row
+// pi(j) -- min over the U rows if q_j > 0, max over the L rows otherwise --
+// with one 16-byte load, and adds q_j * bound for the slots whose bit is set
+// (q_j under the sign-extended bit, so no branches). A lane with none loads
+// from an out-of-range buffer offset, which returns 0 without touching memory,
+// so one vector memory instruction serves 256 slots. Scores never leave
+// registers.
 //
 // Selection keys are ord(score) << 32 | (0xFFFFFFFF - id), so a larger key
 // means a higher score, then a lower id. The tile first finds the k-th largest
@@ -23,12 +24,15 @@
 // score by the lower id the same way, and writes at most k candidates. It then
 // raises the query's shared threshold to its k-th key: no document below it can
 // be in the global top-k, so later tiles keep fewer candidates.
+#include <type_traits>
+
 #include "snn_device.h"
 
 namespace snn {
 
 constexpr uint32_t kBufFlags = 0x00020000u;  // raw buffer resource, 32-bit data format
 constexpr int kOob = (int)0x80000000u;         // buffer offset past every range: load returns 0
+constexpr int kChunk = 4;  // query entries whose posting bits are fetched together
 
 // Sketch rows hold float32 or, with SNN_SKETCH_BF16, bfloat16 values: a lane's
 // 4 slots of a 256-slot group are 16 or 8 consecutive bytes.
@@ -74,6 +78,48 @@ using cptr = const __attribute__((address_space(4))) T *;
 template <typename T>
 __device__ __forceinline__ cptr<T> as_const(const T *p) {
   return (cptr<T>)(p);
+}
+
+// Posting bits of one coordinate for the lane's slots in the wave's G groups:
+// bit 4r + i <-> slot wslot0 + 256r + 4 lane + i. The bitmaps are lane-major in
+// blocks of 1,024 slots, so this is one 2-byte load per lane and block.
+template <int G>
+struct LaneBits {
+  using type = typename std::conditional<(G <= 8), uint32_t, uint64_t>::type;
+};
+
+template <int G>
+__device__ __forceinline__ typename LaneBits<G>::type lane_bits(const DevIndex &ix, uint32_t j, uint32_t wslot0,
+                                                                int lane) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void *)(ix.bits + (size_t)j * ix.W), 0, ix.W * 8u, kBufFlags);
+  const int off = (int)((wslot0 >> 10) * 128u) + lane * 2;
+  if constexpr (G <= 4) {
+    // G = 2: the wave covers half a block, the bits of groups 2 and 3 when it
+    // starts at the second half
+    const uint32_t c = __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0);
+    return c >> ((wslot0 >> 6) & 8u);
+  } else {
+    typename LaneBits<G>::type b = 0;
+#pragma unroll
+    for (int k = 0; k < G / 4; ++k)
+      b |= (typename LaneBits<G>::type)__builtin_amdgcn_raw_buffer_load_b16(rs, off + 128 * k, 0, 0) << (16 * k);
+    return b;
+  }
+}
+
+// the 4 bits of group r
+template <typename T>
+__device__ __forceinline__ bool group_bits(T b, int r) {
+  return ((b >> (4 * r)) & (T)15) != 0;
+}
+
+// q_j where bit x is set, +0 elsewhere (bits of q_j under a sign-extended bit)
+template <typename T>
+__device__ __forceinline__ float masked_q(T b, int x, uint32_t qbits) {
+  const uint32_t w = x < 32 ? (uint32_t)b : (uint32_t)((uint64_t)b >> 32);
+  const uint32_t m = (uint32_t)((int32_t)(w << (31 - (x & 31))) >> 31);
+  return __builtin_bit_cast(float, m & qbits);
 }
 
 struct SelShared {
@@ -151,10 +197,10 @@ __device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&
 template <int R, bool kBf16>
 __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
   constexpr int G = R / 4;  // 256-slot groups per wave
+  using LB = typename LaneBits<G>::type;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
-  const uint32_t wword0 = wslot0 >> 6;
   const DevIndex &ix = a.ix;
 
   if (as_const(a.qd.status)[q] != 0u) {  // malformed query: no candidates
@@ -166,7 +212,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   // For each group the lane loads its 4 slots' bounds with one 16-byte load
   // (out of range, so zeros and no memory traffic, when none of them is on the
   // list) and adds q_j * bound for the slots whose bit is set; absent slots add
-  // q_j * 0 or 0 * (finite stale bound), an exact no-op.
+  // (+0) * bound, an exact no-op.
   float acc[R];
 #pragma unroll
   for (int x = 0; x < R; ++x) acc[x] = 0.0f;
@@ -177,93 +223,78 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   const cptr<uint32_t> qj = as_const(a.qd.j);
   const cptr<float> qq = as_const(a.qd.q);
   const cptr<uint32_t> qb = as_const(a.qd.b);
-  const cptr<uint64_t> bits = as_const(ix.bits);
-  const size_t cap = ix.cap;
-  // One coordinate of the query: wave-uniform bitmap words in SGPRs, one
-  // 16-byte bound load per lane and group, masked FMAs.
-  auto score_one = [&](uint32_t c) {
-    const uint32_t j = qj[e0 + c];
-    const float qv = qq[e0 + c];
-    const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
-    const __amdgpu_buffer_rsrc_t rs = row_rsrc<kBf16, G>(ix, qv > 0.0f, qb[e0 + c] >> 1, wslot0);
-#pragma unroll
-    for (int r = 0; r < G; ++r) {
-      const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
-      const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
-      const int off = any ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob;
-      float v[4];
-      load4<kBf16>(rs, off, v);
-      acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v[0], acc[4 * r + 0]);
-      acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v[1], acc[4 * r + 1]);
-      acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v[2], acc[4 * r + 2]);
-      acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v[3], acc[4 * r + 3]);
-    }
-  };
-  // Two coordinates at a time: their scalar and vector loads are issued
-  // together, so one memory round trip serves both; the adds still go in
-  // coordinate order, so every document's sum is the same as one at a time.
-  auto score_two = [&](uint32_t c) {
-    const uint32_t ja = qj[e0 + c], jb = qj[e0 + c + 1];
-    const float qa = qq[e0 + c], qbv = qq[e0 + c + 1];
-    const cptr<uint64_t> wa = bits + (size_t)ja * ix.W + wword0;
-    const cptr<uint64_t> wb = bits + (size_t)jb * ix.W + wword0;
+  // Two coordinates at a time: their loads are issued together, so one memory
+  // round trip serves both; the adds still go in coordinate order, so every
+  // document's sum is the same as one at a time. A second coordinate past the
+  // end of the list has no bits and adds nothing.
+  auto score_two = [&](uint32_t c, LB ba, uint32_t c2, LB bb) {
+    const float qa = qq[e0 + c], qbv = qq[e0 + c2];
+    const uint32_t qab = __builtin_bit_cast(uint32_t, qa), qbb = __builtin_bit_cast(uint32_t, qbv);
     const __amdgpu_buffer_rsrc_t ra = row_rsrc<kBf16, G>(ix, qa > 0.0f, qb[e0 + c] >> 1, wslot0);
-    const __amdgpu_buffer_rsrc_t rb = row_rsrc<kBf16, G>(ix, qbv > 0.0f, qb[e0 + c + 1] >> 1, wslot0);
+    const __amdgpu_buffer_rsrc_t rb = row_rsrc<kBf16, G>(ix, qbv > 0.0f, qb[e0 + c2] >> 1, wslot0);
 #pragma unroll
     for (int r = 0; r < G; ++r) {
-      const uint64_t a0 = wa[4 * r], a1 = wa[4 * r + 1], a2 = wa[4 * r + 2], a3 = wa[4 * r + 3];
-      const uint64_t b0 = wb[4 * r], b1 = wb[4 * r + 1], b2 = wb[4 * r + 2], b3 = wb[4 * r + 3];
       const int lo = r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane;
-      const int offa = __builtin_amdgcn_inverse_ballot_w64(a0 | a1 | a2 | a3) ? lo : kOob;
-      const int offb = __builtin_amdgcn_inverse_ballot_w64(b0 | b1 | b2 | b3) ? lo : kOob;
+      const int offa = group_bits(ba, r) ? lo : kOob;
+      const int offb = group_bits(bb, r) ? lo : kOob;
       float va[4], vb[4];
       load4<kBf16>(ra, offa, va);
       load4<kBf16>(rb, offb, vb);
-      const uint64_t aw[4] = {a0, a1, a2, a3}, bw[4] = {b0, b1, b2, b3};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float x = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(aw[i]) ? qa : 0.0f, va[i], acc[4 * r + i]);
-        acc[4 * r + i] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(bw[i]) ? qbv : 0.0f, vb[i], x);
+        const float x = __builtin_fmaf(masked_q(ba, 4 * r + i, qab), va[i], acc[4 * r + i]);
+        acc[4 * r + i] = __builtin_fmaf(masked_q(bb, 4 * r + i, qbb), vb[i], x);
       }
     }
   };
-  if (h == 1) {
-    uint32_t c = 0;
-    for (; c + 1 < ne; c += 2) score_two(c);
-    if (c < ne) score_one(c);
-  } else {
-    for (uint32_t c = 0; c < ne; ++c) {
-      const uint32_t j = qj[e0 + c];
-      const float qv = qq[e0 + c];
-      const cptr<uint64_t> wp = bits + (size_t)j * ix.W + wword0;
-      // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows;
-      // unused mappings repeat row 0, which leaves the min / max unchanged
-      const bool upper = qv > 0.0f;
-      __amdgpu_buffer_rsrc_t rs[4];
+  // h > 1: least upper bound (q > 0) or greatest lower bound over the h rows;
+  // unused mappings repeat row 0, which leaves the min / max unchanged
+  auto score_multi = [&](uint32_t c, LB bw) {
+    const float qv = qq[e0 + c];
+    const uint32_t qbits = __builtin_bit_cast(uint32_t, qv);
+    const bool upper = qv > 0.0f;
+    __amdgpu_buffer_rsrc_t rs[4];
 #pragma unroll
-      for (int o = 0; o < 4; ++o) {
-        const uint32_t oo = (uint32_t)o < h ? (uint32_t)o : 0u;
-        rs[o] = row_rsrc<kBf16, G>(ix, upper, qb[(e0 + c) * h + oo], wslot0);
+    for (int o = 0; o < 4; ++o) {
+      const uint32_t oo = (uint32_t)o < h ? (uint32_t)o : 0u;
+      rs[o] = row_rsrc<kBf16, G>(ix, upper, qb[(e0 + c) * h + oo], wslot0);
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const int off = group_bits(bw, r) ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob;
+      float v[4];
+      load4<kBf16>(rs[0], off, v);
+#pragma unroll
+      for (int o = 1; o < 4; ++o) {
+        float x[4];
+        load4<kBf16>(rs[o], off, x);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = upper ? __builtin_fminf(v[i], x[i]) : __builtin_fmaxf(v[i], x[i]);
       }
 #pragma unroll
-      for (int r = 0; r < G; ++r) {
-        const uint64_t w0 = wp[4 * r], w1 = wp[4 * r + 1], w2 = wp[4 * r + 2], w3 = wp[4 * r + 3];
-        const bool any = __builtin_amdgcn_inverse_ballot_w64(w0 | w1 | w2 | w3);
-        const int off = any ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob;
-        float v[4];
-        load4<kBf16>(rs[0], off, v);
+      for (int i = 0; i < 4; ++i) acc[4 * r + i] = __builtin_fmaf(masked_q(bw, 4 * r + i, qbits), v[i], acc[4 * r + i]);
+    }
+  };
+  // The posting bits of kChunk coordinates are fetched together (one 2-byte
+  // load per lane and 1,024-slot block each), so their memory latency is paid
+  // once per chunk rather than once per coordinate.
+  LB cb[kChunk];
+  for (uint32_t c = 0; c < ne;) {
+    if (c % kChunk == 0) {
 #pragma unroll
-        for (int o = 1; o < 4; ++o) {
-          float x[4];
-          load4<kBf16>(rs[o], off, x);
+      for (int k = 0; k < kChunk; ++k) cb[k] = lane_bits<G>(ix, qj[e0 + min(c + (uint32_t)k, ne - 1u)], wslot0, lane);
+    }
+    if (h == 1) {
+      const bool two = c + 1u < ne;
+      score_two(c, cb[0], two ? c + 1u : c, two ? cb[1] : (LB)0);
+      c += 2;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] = upper ? __builtin_fminf(v[i], x[i]) : __builtin_fmaxf(v[i], x[i]);
-        }
-        acc[4 * r + 0] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w0) ? qv : 0.0f, v[0], acc[4 * r + 0]);
-        acc[4 * r + 1] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w1) ? qv : 0.0f, v[1], acc[4 * r + 1]);
-        acc[4 * r + 2] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w2) ? qv : 0.0f, v[2], acc[4 * r + 2]);
-        acc[4 * r + 3] = __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w3) ? qv : 0.0f, v[3], acc[4 * r + 3]);
-      }
+      for (int k = 0; k + 2 < kChunk; ++k) cb[k] = cb[k + 2];
+    } else {
+      score_multi(c, cb[0]);
+      c += 1;
+#pragma unroll
+      for (int k = 0; k + 1 < kChunk; ++k) cb[k] = cb[k + 1];
     }
   }
 
@@ -385,34 +416,52 @@ __device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&
 template <int R, bool kBf16, int Q>
 __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t nq_eff, SelShared &sh) {
   constexpr int G = R / 4;
+  static_assert(G <= 4, "grouped tiles cover at most one 1,024-slot block per wave");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
-  const uint32_t wword0 = wslot0 >> 6;
   const DevIndex &ix = a.ix;
   const cptr<uint32_t> qj = as_const(a.qd.j);
   const cptr<float> qq = as_const(a.qd.q);
   const cptr<uint32_t> qb = as_const(a.qd.b);
-  const cptr<uint64_t> bits = as_const(ix.bits);
   constexpr uint32_t kNone = 0xFFFFFFFFu;
-  // per query: the cursor into its list, the list's end and the sketch row of
-  // the entry under the cursor (none past the end)
-  uint32_t qid[Q], row[Q];
-  uint64_t cur[Q], end[Q];
+  // per query: the cursor into its list and the list's end (32-bit entry
+  // positions: the host keeps a grouped batch below 2^32 entries), the sketch
+  // row of the entry under the cursor (none past the end) and the posting bits
+  // of the next entries, fetched kChunk at a time (cb[i][0] is the cursor's)
+  uint32_t qid[Q], row[Q], left[Q], cur[Q], end[Q];
+  uint32_t cb[Q][kChunk];
+  auto refill = [&](int i) {
+    // the chunk's coordinates in one scalar load (the entry array is padded by
+    // kChunk entries); entries past the list's end fetch the first entry's
+    // bits again and are never used
+    uint32_t js[kChunk];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c) js[c] = qj[cur[i] + (uint32_t)c];
+#pragma unroll
+    for (int c = 0; c < kChunk; ++c)
+      cb[i][c] = lane_bits<G>(ix, cur[i] + (uint32_t)c < end[i] ? js[c] : js[0], wslot0, lane);
+    left[i] = kChunk;
+  };
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const uint32_t slot = grp * (uint32_t)Q + (uint32_t)i;
     qid[i] = kNone;
     cur[i] = end[i] = 0;
+    left[i] = 0;
     if (slot < nq_eff) {
       const uint32_t q = a.qlist ? as_const(a.qlist)[slot] : slot;
       qid[i] = q;
       if (as_const(a.qd.status)[q] == 0u) {
-        cur[i] = as_const(a.qd.qptr)[q] - a.qd.ebase;
+        cur[i] = (uint32_t)(as_const(a.qd.qptr)[q] - a.qd.ebase);
         end[i] = cur[i] + as_const(a.qd.cnt)[q];
       }
     }
-    row[i] = cur[i] < end[i] ? qb[cur[i]] : kNone;
+    row[i] = kNone;
+    if (cur[i] < end[i]) {
+      row[i] = qb[cur[i]];
+      refill(i);
+    }
   }
   float acc[Q][R];
 #pragma unroll
@@ -448,18 +497,21 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       while (row[i] == rmin) {
-        const cptr<uint64_t> wp = bits + (size_t)qj[cur[i]] * ix.W + wword0;
-        const float qv = qq[cur[i]];
+        const uint32_t qbits = __builtin_bit_cast(uint32_t, qq[cur[i]]);
+        const uint32_t bw = cb[i][0];
 #pragma unroll
-        for (int r = 0; r < G; ++r) {
-          const uint64_t w[4] = {wp[4 * r], wp[4 * r + 1], wp[4 * r + 2], wp[4 * r + 3]};
+        for (int r = 0; r < G; ++r)
 #pragma unroll
           for (int k = 0; k < 4; ++k)
-            acc[i][4 * r + k] =
-                __builtin_fmaf(__builtin_amdgcn_inverse_ballot_w64(w[k]) ? qv : 0.0f, v[r][k], acc[i][4 * r + k]);
-        }
+            acc[i][4 * r + k] = __builtin_fmaf(masked_q(bw, 4 * r + k, qbits), v[r][k], acc[i][4 * r + k]);
+#pragma unroll
+        for (int c = 0; c + 1 < kChunk; ++c) cb[i][c] = cb[i][c + 1];
         ++cur[i];
-        row[i] = cur[i] < end[i] ? qb[cur[i]] : kNone;
+        row[i] = kNone;
+        if (cur[i] < end[i]) {
+          row[i] = qb[cur[i]];
+          if (--left[i] == 0) refill(i);
+        }
       }
     }
   }

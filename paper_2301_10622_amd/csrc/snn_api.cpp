@@ -476,7 +476,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   const size_t o_thr = o; o += al((size_t)nq * 4);
   const size_t o_fb = o; o += al((size_t)nq * 4);
   const size_t o_keff = o; o += al((size_t)nq * 4);
-  const size_t o_j = o; o += al((size_t)total * 4);
+  const size_t o_j = o; o += al((size_t)total * 4 + 64);  // the grouped kernel reads up to 16 entries past a list
   const size_t o_q = o; o += al((size_t)total * 4);
   const size_t o_b = o; o += al((size_t)total * 4 * h);
   const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
@@ -717,7 +717,8 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   p.d_sc = d_sc;
   p.d_cnt = d_cnt;
   p.R = mode == SNN_MODE_PLAIN ? tune.R_plain : tune.R_batch;
-  p.qgroup = mode == SNN_MODE_PLAIN || cfg.h != 1 ? 1 : tune.qgroup;
+  // grouped tiles address entries with 32-bit positions
+  p.qgroup = mode == SNN_MODE_PLAIN || cfg.h != 1 || total - o.ebase > 0xFFFFFFF0ull ? 1 : tune.qgroup;
   if (p.qgroup == 1 && p.R < 16) p.R = 16;  // the one-query kernels are built for R >= 16
   p.persistent = mode != SNN_MODE_PLAIN && tune.persistent;
   p.grid = tune.grid;

@@ -1,11 +1,13 @@
 // Device-side data layout and kernel entry points of the Sinnamon library.
 //
 // Layout in HBM (one index):
-//   bits     uint64 [dim][W]      posting bitmaps: bit s of row j is set when the
-//                                 document in slot s has coordinate j in nz(x)
-//                                 (the id-only inverted index I[j] of Section 4.1,
-//                                 stored as a bitmap over slots; W = cap / 64)
-//   live     uint64 [W]           bit s set when slot s holds a live document
+//   bits     uint64 [dim][W]      posting bitmaps: the bit of slot s in row j is set
+//                                 when the document in slot s has coordinate j in
+//                                 nz(x) (the id-only inverted index I[j] of Section
+//                                 4.1, stored as a bitmap over slots; W = cap / 64;
+//                                 bit order post_word / post_bit below)
+//   live     uint64 [W]           bit of slot s (order slot_word / slot_bit) set
+//                                 when slot s holds a live document
 //   U, L     float  [m][cap]      the sketch matrix halves, one contiguous row per
 //                                 bucket (the transposed layout of Section 4.1);
 //                                 bfloat16 with SNN_SKETCH_BF16, no L with
@@ -17,11 +19,16 @@
 //                                 of Alg. 7; per slot its first entry (uint64) and
 //                                 entry count (uint32)
 //
-// Bitmaps are interleaved in groups of 256 slots so that a 64-bit word is a
-// wavefront lane mask while each lane still reads 4 adjacent sketch values at
-// once: in group g (slots 256g .. 256g+255), word 4g + i has bit l set for slot
-// 256g + 4l + i. Lane l of a wave owns slots 4l .. 4l+3 of each of its groups,
-// so no lane ever contends with another for a score.
+// Lane l of a wave owns slots 4l .. 4l+3 of each 256-slot group it covers, so
+// it reads their 4 sketch values with one load and no lane ever contends with
+// another for a score. The live and dirty bitmaps are interleaved by group so
+// that a 64-bit word is a wavefront lane mask: in group g (slots 256g ..
+// 256g+255), word 4g + i has bit l set for slot 256g + 4l + i. The posting
+// bitmaps are lane-major inside each block of 1,024 slots (4 groups): the 16
+// bits of lane l -- slot 256g + 4l + i of the block at bit 4g + i -- form the
+// block's 16-bit chunk l, so a wave reads its lanes' bits of one coordinate
+// with a 2-byte load per lane (128 contiguous bytes) and many coordinates'
+// bits can be in flight at once in vector registers.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -120,8 +127,15 @@ struct SelectArgs {
   uint32_t *res_slots;         // [nq][kmax] slots of the results (with in_slot)
 };
 
+// live / dirty bitmaps: word and bit of a slot
 __host__ __device__ inline uint32_t slot_word(uint32_t slot) { return ((slot >> 8) << 2) | (slot & 3u); }
 __host__ __device__ inline uint32_t slot_bit(uint32_t slot) { return (slot >> 2) & 63u; }
+// posting bitmaps: word and bit of a slot inside a row (block slot >> 10, lane
+// l = (slot >> 2) & 63 in word l / 4 at bits 16 (l % 4) + 4g + i)
+__host__ __device__ inline uint32_t post_word(uint32_t slot) { return ((slot >> 10) << 4) | ((slot >> 4) & 15u); }
+__host__ __device__ inline uint32_t post_bit(uint32_t slot) {
+  return (((slot >> 2) & 3u) << 4) | (((slot >> 8) & 3u) << 2) | (slot & 3u);
+}
 
 // order-preserving float -> uint32 map (negative floats reversed); 0 never occurs for finite x
 __host__ __device__ inline uint32_t ord_key(float x) {
