@@ -71,8 +71,8 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const DevIndex &ix, b
 }
 
 // Read-only arrays are read through the constant address space: with a
-// wave-uniform address the loads become scalar loads (s_load), so bitmap words
-// and query entries land in SGPRs and drive the lane masks directly.
+// wave-uniform address the loads become scalar loads (s_load), so query entries
+// and the live / dirty words land in SGPRs (the latter drive lane masks directly).
 template <typename T>
 using cptr = const __attribute__((address_space(4))) T *;
 template <typename T>
@@ -184,8 +184,8 @@ __device__ __forceinline__ uint32_t count_pred(const bool (&p)[R]) {
 }
 
 // Slot layout inside a 256-slot group (see snn_device.h): lane l owns slots
-// 4l .. 4l+3; bitmap word i of the group has bit l set when slot 4l + i is
-// present. Register index x = 4r + i of a lane is slot wslot0 + 256r + 4l + i.
+// 4l .. 4l+3; live / dirty word i of the group has bit l set for slot 4l + i.
+// Register index x = 4r + i of a lane is slot wslot0 + 256r + 4l + i.
 template <int R>
 __device__ __forceinline__ uint32_t slot_of(uint32_t wslot0, int x, int lane) {
   return wslot0 + 256u * (uint32_t)(x >> 2) + 4u * (uint32_t)lane + (uint32_t)(x & 3);

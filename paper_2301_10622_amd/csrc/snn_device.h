@@ -65,8 +65,11 @@ struct DevForward {
   uint32_t *len;     // [cap] its number of entries
 };
 
-// Prepared queries (Alg. 6 first steps): entry e of query q sits at qptr[q] + i
-// for i < cnt[q], sorted by |q_j| descending, ties by lower j.
+// Prepared queries (Alg. 6 first steps): entry i < cnt[q] of query q sits at
+// qptr[q] + i. The entries are the query's first cnt[q] coordinates in the
+// order |q_j| descending, ties by lower j; with h = 1 they are then stored by
+// sketch row (b), ties in that order, so that a document's terms are added row
+// by row whichever kernel scores it.
 struct QueryDesc {
   const uint64_t *qptr;  // [nq + 1] (the caller's CSR offsets; entry e sits at e - ebase below)
   uint32_t *cnt;         // [nq] non-zero entries after preparation
