@@ -529,6 +529,13 @@ def serving_8m(args, dev, P, gen, np, torch):
     P.load_docs(ix, docs)
     ops = args.serving_ops
     res = {"workload": "serving capacity 8M, 4M prefill, %d ops, 85/10/5 search/insert/delete" % ops}
+    # the batched schedule, tuned on 1,024 queries of the serving law at k = 100
+    sq = gen.serving_queries(7, 1024)
+    et = (torch.tensor(sq.indptr, dtype=torch.int64, device=dev), torch.tensor(sq.coords.astype(np.int32), device=dev),
+          torch.tensor(sq.vals, device=dev))
+    res["schedule"] = ix.autotune(*et, 100, total=int(sq.nnz))
+    del et
+    log("serving: schedule %s" % res["schedule"])
     budget = 8 << 30
 
     live = {"ids": np.arange(docs.rows, dtype=np.int64)}

@@ -53,10 +53,14 @@ def _oracle_for(state):
     return O.Index(csr, 1000, 32, 1, 0, ids=ids), csr, ids
 
 
-def test_serving_results_equal_alone_at_their_snapshot():
+@pytest.mark.parametrize("qgroup", [1, 2])
+def test_serving_results_equal_alone_at_their_snapshot(qgroup):
+    """Both the one-query and the grouped (two queries per workgroup) batched
+    kernels serve the trace; the results are the same bits as a search alone."""
     import paper_2301_10622_amd as P
 
     ix, docs = _setup()
+    ix.set_schedule(16, 16, 2048, True, qgroup)
     tr, csr = _trace(0, 3000, np.arange(docs.rows), docs.rows, rate=20000.0)
     res_ids, res_sc, res_cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords,
                                                   csr.vals, max_batch=256, max_inflight=3, streams=3, realtime=True,
