@@ -253,6 +253,8 @@ def main():
     if traffic:
         roofline["traffic_GBps"] = round(traffic / (launch_ms / 1000.0) / 1e9, 1)
         roofline["traffic_over_alg_bytes"] = round(traffic / ab_launch, 4)
+    # what this machine's HBM delivers to a plain device copy, beside the published peak
+    roofline["copy_GBps"] = round(measured_copy_gbps(torch, dev), 1)
 
     result = {
         "metric": METRIC, "value": round(head["qps"], 1), "unit": "queries/s", "n_gpus": 1,
@@ -348,6 +350,27 @@ def main():
     if not args.no_serving:
         result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def measured_copy_gbps(torch, dev, mib=1024, reps=10):
+    """Achievable HBM bandwidth: a 1 GiB device-to-device copy (bytes read +
+    bytes written per second), best of `reps` after one warm-up, on the current
+    stream."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (best / 1000.0) / 1e9
 
 
 def tile_kernel_name(sched, form):
