@@ -599,17 +599,17 @@ __global__ __launch_bounds__(kBlock) void k_tiles_grouped(TileArgs a) {
   tile_group<R, kBf16, Q>(a, grp, blockIdx.x, nq, sh);
 }
 
-// Waves per SIMD the persistent grouped kernel is built for: with R = 16 and
-// two queries the register file holds 8 (64 VGPRs, a few spilled around the
-// selection), which is measurably faster than 7; other shapes are left to the
-// compiler (they spill in the scoring loop at 8).
-template <int R, int Q>
+// Waves per SIMD the persistent grouped kernel is built for: with R = 16, two
+// queries and a float32 sketch the register file holds 8 (64 VGPRs, a few
+// spilled around the selection), which is measurably faster than 7; the other
+// shapes, bfloat16 included, are left to the compiler (they are slower at 8).
+template <int R, bool kBf16, int Q>
 struct GroupedWaves {
-  static constexpr int value = (R == 16 && Q == 2) ? 8 : 1;
+  static constexpr int value = (R == 16 && Q == 2 && !kBf16) ? 8 : 1;
 };
 
 template <int R, bool kBf16, int Q>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GroupedWaves<R, Q>::value)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GroupedWaves<R, kBf16, Q>::value)))
 void k_tiles_persistent_grouped(TileArgs a) {
   __shared__ SelShared sh;
   const uint32_t X = a.xcds;
