@@ -169,7 +169,7 @@ typedef struct {
 
 /* Device-pointer batch search with options; arguments otherwise as in
  * snn_search_batch_dev. Errors: SNN_E_INVALID (k = 0 or > 4096, nq = 0, an
- * unknown mode, 0 < k' < k, k' > 4096, re-rank outside SNN_MODE_BATCHED or
+ * unknown mode, 0 < k' < k, k' > 65,536, re-rank outside SNN_MODE_BATCHED or
  * without a forward store, reserved != 0), SNN_E_NOMEM, SNN_E_DEVICE. */
 snn_status snn_search_ex_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
                              const uint32_t *coords, const float *vals, uint32_t k, const snn_search_params *params,
@@ -187,8 +187,13 @@ snn_status snn_search_ex(snn_index *ix, uint32_t nq, const uint64_t *indptr, con
  * returned, ties by the lower external id. out_scores hold those exact
  * scores. Needs an index created with SNN_FORWARD_STORE. Device pointers and
  * stream as in snn_search_batch_dev; outputs are nq x k and nq counts of
- * min(k, k_prime, live). Errors: SNN_E_INVALID (no forward store, k = 0,
- * k_prime < k or k_prime > 4096, nq = 0), SNN_E_NOMEM, SNN_E_DEVICE. */
+ * min(k, k_prime, live). When k_prime exceeds a tile (256 R slots), which no
+ * tile's own selection can cut, the search first selects on a sample of the
+ * tiles (one in 16) and starts the full pass from the lowest score of about
+ * 2 k_prime / 16 best there; a query that then keeps fewer than
+ * min(k_prime, live) candidates runs again without it, so the results are
+ * those of Alg. 7 either way. Errors: SNN_E_INVALID (no forward store, k = 0,
+ * k_prime < k or k_prime > 65,536, nq = 0), SNN_E_NOMEM, SNN_E_DEVICE. */
 snn_status snn_search_rerank_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
                                  const uint32_t *coords, const float *vals, uint32_t k, uint32_t k_prime,
                                  uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream);
@@ -200,12 +205,15 @@ snn_status snn_search_rerank(snn_index *ix, uint32_t nq, const uint64_t *indptr,
                              uint32_t *out_counts);
 
 /* Number of queries of the last snn_search_batch_dev call that were malformed
- * (needs the stream synchronised), and, for SNN_MODE_LEARNED, how many fell
- * back to the plain path. */
+ * (needs the stream synchronised), and, for SNN_MODE_LEARNED and for a
+ * re-ranking search whose k' exceeds a tile, how many fell back to the pass
+ * without a starting threshold. */
 snn_status snn_last_batch_status(snn_index *ix, uint32_t *invalid_queries, uint32_t *fallbacks);
 
-/* Selection work of the last batch search (both passes of SNN_MODE_LEARNED
- * counted apart; the *_fallback fields are 0 in the other modes):
+/* Selection work of the last batch search (the filtered and the fallback pass
+ * counted apart: SNN_MODE_LEARNED, and a re-ranking search whose k' exceeds a
+ * tile, which starts from thresholds found on a sample of the tiles; the
+ * *_fallback fields are 0 otherwise):
  *   candidates  keys the tiles handed to the merge, i.e. the insertions into
  *               the top-k selection of Alg. 3 that survived each tile's own
  *               selection;

@@ -1,6 +1,8 @@
 // Merge of the per-tile candidates of each query into its final top-k
 // (selection of Alg. 3 / Alg. 7 over the tile winners), and the fallback list
 // of the learned filter.
+#include <algorithm>
+
 #include "snn_device.h"
 
 namespace snn {
@@ -192,6 +194,40 @@ hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
   if (sorted && !pay) hipLaunchKernelGGL((k_select<false, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
   else if (!sorted && pay) hipLaunchKernelGGL((k_select<true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
   else return hipErrorInvalidValue;  // the two forms the search uses
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Starting threshold of a search whose k' exceeds a tile (Alg. 7): the lowest
+// score among the ks best of a sample of the tiles, as an inclusive score key;
+// 0 (no threshold) when the sample held fewer than ks candidates. One
+// workgroup per query.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sample_thr(uint32_t ks, uint32_t stride, const float *__restrict__ sc,
+                                                    const uint32_t *__restrict__ cnt, uint32_t *__restrict__ thr) {
+  __shared__ float red[256];
+  const uint32_t q = blockIdx.x;
+  const uint32_t c = cnt[q];
+  float m = __builtin_inff();
+  for (uint32_t i = threadIdx.x; i < c; i += 256) m = fminf(m, sc[(size_t)q * stride + i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int d = 128; d > 0; d >>= 1) {
+    if (threadIdx.x < (unsigned)d) red[threadIdx.x] = fminf(red[threadIdx.x], red[threadIdx.x + d]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) thr[q] = (c >= ks && ks > 0) ? ord_key(red[0]) : 0u;
+}
+
+hipError_t launch_sample_thr(uint32_t nq, uint32_t ks, uint32_t stride, const float *sc, const uint32_t *cnt,
+                             uint32_t *thr, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  if (ks > stride) return hipErrorInvalidValue;
+  for (uint32_t q0 = 0; q0 < nq; q0 += 65535u) {
+    const uint32_t n = std::min<uint32_t>(65535u, nq - q0);
+    hipLaunchKernelGGL(k_sample_thr, dim3(n), dim3(256), 0, s, ks, stride, sc + (size_t)q0 * stride, cnt + q0,
+                       thr + q0);
+  }
   return hipGetLastError();
 }
 

@@ -485,6 +485,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   const size_t o_nlist = o; o += al(4);
   const size_t o_stats = o; o += al(32);
   const size_t o_nz = o; o += al((size_t)nq * 4);
+  const size_t o_sthr = o; o += al((size_t)nq * 4);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
   HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * kt * 8 + 64, stream), "candidate buffer");
   char *p = (char *)W.ws.p;
@@ -502,6 +503,7 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   w.nlist = (uint32_t *)(p + o_nlist);
   w.stats = (unsigned long long *)(p + o_stats);
   w.nz_full = (uint32_t *)(p + o_nz);
+  w.sthr = (uint32_t *)(p + o_sthr);
   w.cand = (uint64_t *)W.cand.p;
   w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
@@ -568,13 +570,6 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     HIP_TRY(this, launch_threshold(p.nq, lp->yhat, lp->delta, lp->keff_value, lp->thr, lp->keff, s), "threshold");
   }
   HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, o.max_coords, w.nz_full, s), "prep kernel");
-  const uint32_t *thr_init = lp ? lp->thr : o.thr_init;
-  const uint32_t *keff = lp ? lp->keff : o.keff;
-  if (thr_init) {
-    HIP_TRY(this, launch_copy_u32(w.thr, thr_init, p.nq, s), "thr init");
-  } else {
-    HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
-  }
   HIP_TRY(this, launch_fill_u32((uint32_t *)w.stats, 0u, 8, s), "stats fill");
   TileArgs a{};
   a.ix = dev;
@@ -599,7 +594,6 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   mj.k = p.k;
   mj.in_stride = p.kt;
   mj.kq = o.kq;
-  mj.keff = keff;
   mj.res_ids = rerank ? w.rr_ids : p.d_ids;
   mj.res_scores = rerank ? w.rr_sc : p.d_sc;
   mj.res_cnt = rerank ? w.rr_cnt : p.d_cnt;
@@ -609,6 +603,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   mj.emitted = w.stats;
   mj.set_fallback = true;
   if (p.mode == SNN_MODE_PLAIN) {
+    HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
     for (uint32_t q = 0; q < p.nq; ++q) {
       a.q0 = q;
       hipEvent_t e0 = prof_on ? prof_event() : nullptr;
@@ -655,12 +650,72 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     if (e1) HIP_TRY(this, hipEventRecord(e1, s), "event");
     return SNN_OK;
   };
-  snn_status st = tiles_pass(ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
+  snn_status st = SNN_OK;
+  // Starting thresholds and the count each query must keep: from the learned
+  // filter, or, when k' exceeds a tile, from a first pass over a sample of the
+  // tiles (the lowest score among the k_s best there); queries that keep fewer
+  // candidates run again without a threshold, so the results never change.
+  const uint32_t *thr_init = o.thr_init, *keff = o.keff;
+  if (lp) {
+    thr_init = lp->thr;
+    keff = lp->keff;
+  } else if (p.tiles_s) {
+    HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
+    a.tiles = p.tiles_s;
+    a.kmax = std::min(p.k_s, p.kt);
+    a.nselect = nullptr;
+    st = tiles_pass(nullptr, nullptr);
+    if (st != SNN_OK) return st;
+    MergeJob m1 = mj;
+    m1.tiles = p.tiles_s;
+    m1.k = p.k_s;
+    m1.in_stride = a.kmax;
+    m1.kq = nullptr;
+    m1.emitted = nullptr;
+    m1.set_fallback = false;
+    m1.q0 = 0;
+    m1.nqm = p.nq;
+    st = enqueue_merge(w, m1, s);
+    if (st != SNN_OK) return st;
+    // the select wrote each query's k_s results at stride k_s
+    HIP_TRY(this, launch_sample_thr(p.nq, p.k_s, p.k_s, w.rr_sc, w.rr_cnt, w.sthr, s), "sample threshold");
+    HIP_TRY(this, launch_fill_u32(w.keff, (uint32_t)std::min<size_t>(p.k, live), p.nq, s), "keff fill");
+    a.tiles = p.tiles;
+    a.kmax = p.kt;
+    a.nselect = w.stats + 2;
+    thr_init = w.sthr;
+    keff = w.keff;
+  }
+  if (thr_init) {
+    HIP_TRY(this, launch_copy_u32(w.thr, thr_init, p.nq, s), "thr init");
+  } else {
+    HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
+  }
+  mj.keff = keff;
+  st = tiles_pass(ev ? ev[0] : nullptr, ev ? ev[1] : nullptr);
   if (st != SNN_OK) return st;
   mj.q0 = 0;
   mj.nqm = p.nq;
   st = enqueue_merge(w, mj, s);
   if (st != SNN_OK) return st;
+  if (thr_init && keff) {
+    // the queries that kept fewer than keff candidates, again with no threshold
+    HIP_TRY(this, launch_fallback_list(p.nq, w.fallback, w.qlist, w.nlist, w.thr, s), "fallback list");
+    a.qlist = w.qlist;
+    a.nlist = w.nlist;
+    a.nselect = w.stats + 3;
+    st = tiles_pass(ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+    if (st != SNN_OK) return st;
+    a.qlist = a.nlist = nullptr;
+    MergeJob mf = mj;
+    mf.keff = nullptr;
+    mf.set_fallback = false;
+    mf.qlist = w.qlist;
+    mf.nlist = w.nlist;
+    mf.emitted = w.stats + 1;
+    st = enqueue_merge(w, mf, s);
+    if (st != SNN_OK) return st;
+  }
   if (rerank) {
     RerankArgs r{};
     r.fw = fw;
@@ -676,6 +731,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     // the k best of the k' exact scores, in order
     MergeJob fin;
     fin.k = o.rerank_k;
+    fin.sorted = true;
     fin.in = w.rk;
     fin.in_cnt = w.rr_cnt;
     fin.in_stride = p.k;
@@ -687,20 +743,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     st = enqueue_merge(w, fin, s);
     if (st != SNN_OK) return st;
   }
-  if (!lp) return SNN_OK;
-  // plain fallback of the learned filter, over the flagged queries only
-  HIP_TRY(this, launch_fallback_list(p.nq, w.fallback, w.qlist, w.nlist, w.thr, s), "fallback list");
-  a.qlist = w.qlist;
-  a.nlist = w.nlist;
-  a.nselect = w.stats + 3;
-  st = tiles_pass(ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
-  if (st != SNN_OK) return st;
-  mj.keff = nullptr;
-  mj.set_fallback = false;
-  mj.qlist = w.qlist;
-  mj.nlist = w.nlist;
-  mj.emitted = w.stats + 1;
-  return enqueue_merge(w, mj, s);
+  return SNN_OK;
 }
 
 snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
@@ -726,6 +769,21 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
   p.kt = std::min<uint32_t>(k, tile_docs);
+  // k' above a tile: no tile can raise a query's threshold by itself, so every
+  // live document would become a candidate. A first pass over the first
+  // tiles / kSampleStride tiles selects the k_s best there, k_s chosen so that
+  // about 2 k' documents of the whole collection score at least the lowest of
+  // them (a slot range holds a random sample of the collection's documents;
+  // when it does not, more queries run the no-threshold pass, nothing else)
+  p.tiles_s = p.k_s = 0;
+  if (o.rerank_k != 0 && mode == SNN_MODE_BATCHED && k > tile_docs && p.tiles >= 4 * kSampleStride) {
+    const uint32_t ts = p.tiles / kSampleStride;
+    const uint64_t ks = (2ull * k * ts + p.tiles - 1) / p.tiles + 32;
+    if (ks < k) {
+      p.tiles_s = ts;
+      p.k_s = (uint32_t)ks;
+    }
+  }
   return prepare_workspace(nq, total - o.ebase, p.kt, p.tiles, o.rerank_k ? k : 0, p.w, o.wsp ? *o.wsp : wsp, s);
 }
 
@@ -745,12 +803,12 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   last_ws = p.w;
   last_status = p.w.status;
   last_stats = p.w.stats;
-  last_nlist = o.learned ? p.w.nlist : nullptr;
+  last_nlist = o.learned || p.tiles_s ? p.w.nlist : nullptr;
   // graphs need a capturable stream (the legacy default stream is not one);
   // timed (profiled) passes launch eagerly so events can bracket the tile kernel
   if (mode == SNN_MODE_PLAIN || !use_graphs || s == nullptr || prof_on || o.no_graph) {
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    const int nev = prof_on && mode != SNN_MODE_PLAIN ? (o.learned ? 4 : 2) : 0;
+    const int nev = prof_on && mode != SNN_MODE_PLAIN ? (o.learned || p.tiles_s ? 4 : 2) : 0;
     for (int i = 0; i < nev; ++i) ev[i] = prof_event();
     st = enqueue_search(p, o, s, nev ? ev : nullptr);
     for (int i = 0; i < nev; ++i) prof_events.push_back(ev[i]);

@@ -48,12 +48,17 @@ struct SearchWs {
   uint64_t *cand = nullptr;
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
   uint32_t *nz_full = nullptr;                  // [nq] whole non-zero count of each prepared query
+  uint32_t *sthr = nullptr;                     // [nq] starting thresholds from a sample of the tiles
   uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
   uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' selected candidates
   float *rr_sc = nullptr;
   uint64_t *rk = nullptr;                       // re-rank: their exact-score keys
   unsigned long long *stats = nullptr;          // candidates emitted, selecting tiles (main, fallback pass)
 };
+
+// A search whose k' exceeds a tile samples one tile in kSampleStride for its
+// starting thresholds.
+constexpr uint32_t kSampleStride = 16;
 
 // Launch schedule of the search kernels (set by the autotuner).
 struct Tune {
@@ -113,6 +118,9 @@ struct MergeJob {
 struct SearchPlan {
   uint32_t nq = 0, k = 0, tiles = 0, grid = 0;
   uint32_t kt = 0;  // candidates one tile keeps per query: min(k, slots per tile)
+  // k above a tile (re-rank): a first pass over tiles_s tiles selects the k_s
+  // best there, whose lowest score starts the threshold of the full pass
+  uint32_t tiles_s = 0, k_s = 0;
   int mode = 0, R = 16, qgroup = 1;
   bool persistent = false;
   uint64_t total = 0;

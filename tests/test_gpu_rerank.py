@@ -202,3 +202,85 @@ def test_rerank_gaussian_law_k1000_kprime20000():
             parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
                                       what="g100-law c=%d q%d" % (c, qi))
     ix.close()
+
+
+def _sampled_case(docs, queries, boost_rows=0, law="small"):
+    P = _lib()
+    if law == "small":
+        w = gen.make_small(3, docs=docs, queries=queries)
+    else:
+        w = gen.make_gaussian(1, 100, docs=docs, queries=queries)
+    d = w.docs
+    if boost_rows:
+        # the first documents (the first tiles) hold the largest values, so the
+        # sample's thresholds are too high for the whole collection
+        d = gen.CSR(d.indptr, d.coords, d.vals.copy())
+        d.vals[: int(d.indptr[boost_rows])] *= 8.0
+    ix = P.Index(w.n, w.m, w.h, capacity=d.rows, hash_seed=w.hash_seed, forward_store=True)
+    P.load_docs(ix, d)
+    ora = O.Index(d, w.n, w.m, w.h, w.hash_seed)
+    return w, d, ix, ora
+
+
+def _search_two_ways(ix, q, k, kp, c=0):
+    """The search with 4,096-slot tiles (k' above a tile: sampled thresholds)
+    and with 16,384-slot tiles (too few tiles to sample: no starting
+    threshold). Every schedule adds the same terms in the same order, so the
+    two must agree bit for bit."""
+    ix.set_schedule(16, 16, 2048, True)
+    got = ix.search_ex(q.indptr, q.coords, q.vals, k, k_prime=kp, max_coords=c)
+    work = ix.last_batch_work()
+    _, fallbacks = ix.last_batch_status()
+    ix.set_schedule(16, 64, 2048, True)
+    ref = ix.search_ex(q.indptr, q.coords, q.vals, k, k_prime=kp, max_coords=c)
+    _, fb_ref = ix.last_batch_status()
+    assert fb_ref == 0
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    return got, work, fallbacks
+
+
+def test_rerank_kprime_above_tile_starts_from_sampled_thresholds():
+    """k' = 5,000 over 300,000 documents (74 tiles of 4,096): the first pass over
+    4 sampled tiles gives each query a starting threshold, and the full pass
+    hands the selection about 2 k' candidates per query instead of every
+    document. Results: bit-identical to the search without it, and valid
+    Alg. 7 results against the oracle."""
+    w, d, ix, ora = _sampled_case(300_000, 8)
+    q = w.queries
+    (ids, sc, cnt), work, fallbacks = _search_two_ways(ix, q, 10, 5000)
+    assert fallbacks == 0
+    assert 0 < work["candidates"] < q.rows * 4 * 5000, work
+    _check(ids, sc, cnt, ora, q, 10, 5000, "sampled")
+    ix.close()
+
+
+def test_rerank_sampled_thresholds_fall_back_when_the_sample_misleads():
+    """The first 20,000 documents carry 8x larger values, so a threshold from the
+    first tiles lets fewer than k' documents through: every query runs again
+    with no threshold, and the results are unchanged."""
+    w, d, ix, ora = _sampled_case(300_000, 6, boost_rows=20_000)
+    q = w.queries
+    (ids, sc, cnt), work, fallbacks = _search_two_ways(ix, q, 10, 5000)
+    assert fallbacks == q.rows and work["candidates_fallback"] > 0
+    _check(ids, sc, cnt, ora, q, 10, 5000, "sampled fallback")
+    ix.close()
+
+
+def test_rerank_sampled_thresholds_gaussian_law_k1000_kprime20000():
+    """The G100 law at 320,000 documents with k = 1,000 and k' = 20,000 (78
+    tiles, so the sampled first pass runs), full and anytime."""
+    w, d, ix, ora = _sampled_case(320_000, 5, law="gaussian")
+    q = w.queries
+    ids_of_pos = ora.ids.astype(np.int64)
+    for c in (0, 30):
+        (ids, sc, cnt), work, fallbacks = _search_two_ways(ix, q, 1000, 20000, c)
+        assert fallbacks == 0
+        for qi in range(q.rows):
+            qc, qv = q.row(qi)
+            est, ea = ora.score_all(qc, qv, max_coords=c)
+            ex, xa = ora.score_all(qc, qv, exact=True)
+            n = int(cnt[qi])
+            parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
+                                      what="g100-law sampled c=%d q%d" % (c, qi))
+    ix.close()
