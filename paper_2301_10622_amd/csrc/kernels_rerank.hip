@@ -3,7 +3,8 @@
 // scored with the exact inner product of Eq. 2. The k best by exact score
 // (ties by the lower external id) are then picked by the select kernel.
 //
-// One workgroup of 8 waves per query. The query's non-zeros (all of them,
+// One workgroup of 8 waves per (query, share of its candidates); a small batch
+// spreads each query's candidates over several workgroups. The query's non-zeros (all of them,
 // whatever the anytime budget of the scoring) go into an open-addressing hash
 // table in LDS (coordinate -> value), so a document entry costs one LDS probe
 // whatever the dimensionality. Each wave takes 64 candidates at a time: lane l
@@ -40,6 +41,10 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
   const uint64_t e0 = a.qd.qptr[q] - a.qd.ebase;
   const int tid = threadIdx.x;
   if (2u * ne > cap) return;  // the launcher sizes the table for every query; never taken
+  // this workgroup's share [lo, hi) of the query's candidates
+  const uint32_t share = ((n + gridDim.y - 1) / gridDim.y + 63u) & ~63u;
+  const uint32_t lo = blockIdx.y * share, hi = min(n, lo + share);
+  if (lo >= hi) return;
 
   // the query as a hash table: linear probing, at most half full
   for (uint32_t i = tid; i < cap; i += kRrBlock) hk[i] = kEmpty;
@@ -69,20 +74,20 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
     }
   };
 
-  // exact inner products
+  // exact inner products of this workgroup's share of the candidates
   const int lane = tid & 63, wave = tid >> 6;
   const size_t cbase = (size_t)q * a.kprime;
-  for (uint32_t base = (uint32_t)wave * 64u; base < n; base += (uint32_t)kRrBlock) {
+  for (uint32_t base = lo + (uint32_t)wave * 64u; base < hi; base += (uint32_t)kRrBlock) {
     const uint32_t c = base + (uint32_t)lane;
     uint32_t id = 0, len = 0;
     uint64_t off = 0;
-    if (c < n) {
+    if (c < hi) {
       const uint32_t slot = a.cand_slots[cbase + c];
       id = a.cand_ids[cbase + c];
       off = a.fw.off[slot];
       len = a.fw.len[slot];
     }
-    const uint32_t here = min(64u, n - base);
+    const uint32_t here = min(64u, hi - base);
     for (uint32_t t = 0; t < here; ++t) {
       const uint64_t o = ((uint64_t)shfl_u32((uint32_t)(off >> 32), (int)t) << 32) | shfl_u32((uint32_t)off, (int)t);
       const uint32_t ln = shfl_u32(len, (int)t);
@@ -112,10 +117,15 @@ hipError_t launch_rerank(const RerankArgs &a, uint32_t nq, hipStream_t s) {
       (a.hash_cap & (a.hash_cap - 1)) || !a.fw.ent || !a.keys)
     return hipErrorInvalidValue;
   const size_t lds = (size_t)a.hash_cap * 8;
+  // workgroups per query: enough to fill the device for small batches, and at
+  // least 512 candidates each
+  const uint32_t by_grid = std::max<uint32_t>(1u, 1024u / nq);
+  const uint32_t by_work = std::max<uint32_t>(1u, a.kprime / 512u);
+  const uint32_t splits = std::min<uint32_t>(64u, std::min(by_grid, by_work));
   for (uint32_t c0 = 0; c0 < nq; c0 += 65535u) {
     RerankArgs b = a;
     b.q0 = a.q0 + c0;
-    hipLaunchKernelGGL(k_rerank, dim3(std::min<uint32_t>(65535u, nq - c0)), dim3(kRrBlock), lds, s, b);
+    hipLaunchKernelGGL(k_rerank, dim3(std::min<uint32_t>(65535u, nq - c0), splits), dim3(kRrBlock), lds, s, b);
   }
   return hipGetLastError();
 }

@@ -769,14 +769,16 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
   p.kt = std::min<uint32_t>(k, tile_docs);
-  // k' above a tile: no tile can raise a query's threshold by itself, so every
-  // live document would become a candidate. A first pass over the first
-  // tiles / kSampleStride tiles selects the k_s best there, k_s chosen so that
-  // about 2 k' documents of the whole collection score at least the lowest of
-  // them (a slot range holds a random sample of the collection's documents;
-  // when it does not, more queries run the no-threshold pass, nothing else)
+  // A wide k' (a sixteenth of a tile or more): a tile's own selection keeps the
+  // tile's k' best, a large share of it (all of it when k' reaches the tile), so
+  // a query hands the selection tiles x min(k', tile) candidates. A first pass
+  // over the first tiles / kSampleStride tiles selects the k_s best there, k_s
+  // chosen so that about 2 k' documents of the whole collection score at least
+  // the lowest of them (a slot range holds a random sample of the collection's
+  // documents; when it does not, more queries run the no-threshold pass,
+  // nothing else)
   p.tiles_s = p.k_s = 0;
-  if (o.rerank_k != 0 && mode == SNN_MODE_BATCHED && k > tile_docs && p.tiles >= 4 * kSampleStride) {
+  if (o.rerank_k != 0 && mode == SNN_MODE_BATCHED && (uint64_t)k * 16 >= tile_docs && p.tiles >= 4 * kSampleStride) {
     const uint32_t ts = p.tiles / kSampleStride;
     const uint64_t ks = (2ull * k * ts + p.tiles - 1) / p.tiles + 32;
     if (ks < k) {
