@@ -231,6 +231,20 @@ hipError_t launch_sample_thr(uint32_t nq, uint32_t ks, uint32_t stride, const fl
   return hipGetLastError();
 }
 
+// keff[q] = min(k of query q, cap): the candidates query q must keep so that a
+// starting threshold cannot have cut its top-k
+__global__ __launch_bounds__(256) void k_keff(uint32_t nq, const uint32_t *__restrict__ kq, uint32_t kmax,
+                                              uint32_t cap, uint32_t *__restrict__ keff) {
+  const uint32_t q = blockIdx.x * 256 + threadIdx.x;
+  if (q < nq) keff[q] = min(kq ? kq[q] : kmax, cap);
+}
+
+hipError_t launch_keff(uint32_t nq, const uint32_t *kq, uint32_t kmax, uint32_t cap, uint32_t *keff, hipStream_t s) {
+  if (nq == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_keff, dim3((nq + 255) / 256), dim3(256), 0, s, nq, kq, kmax, cap, keff);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Fallback list of the learned filter: one workgroup compacts the queries whose
 // filtered merge kept fewer than the required candidates, in query order, into

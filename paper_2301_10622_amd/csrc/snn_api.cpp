@@ -467,7 +467,7 @@ extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete
 // candidates. Laid out in one allocation.
 // kt: candidates a tile keeps per query; kprime > 0: the re-rank's buffers too.
 snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime,
-                                        SearchWs &w, Workspace &W, hipStream_t stream) {
+                                        uint32_t ksample, SearchWs &w, Workspace &W, hipStream_t stream) {
   const uint32_t h = cfg.h;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t o = 0;
@@ -486,6 +486,10 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   const size_t o_stats = o; o += al(32);
   const size_t o_nz = o; o += al((size_t)nq * 4);
   const size_t o_sthr = o; o += al((size_t)nq * 4);
+  const size_t ks = ksample <= kMaxK ? ksample : 0;  // larger samples select into the re-rank buffers
+  const size_t o_ssi = o; o += al((size_t)nq * ks * 4);
+  const size_t o_sss = o; o += al((size_t)nq * ks * 4);
+  const size_t o_ssc = o; o += al((size_t)nq * 4);
   HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
   HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * kt * 8 + 64, stream), "candidate buffer");
   char *p = (char *)W.ws.p;
@@ -504,6 +508,9 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   w.stats = (unsigned long long *)(p + o_stats);
   w.nz_full = (uint32_t *)(p + o_nz);
   w.sthr = (uint32_t *)(p + o_sthr);
+  w.ss_ids = (uint32_t *)(p + o_ssi);
+  w.ss_sc = (float *)(p + o_sss);
+  w.ss_cnt = (uint32_t *)(p + o_ssc);
   w.cand = (uint64_t *)W.cand.p;
   w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
@@ -675,11 +682,19 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     m1.set_fallback = false;
     m1.q0 = 0;
     m1.nqm = p.nq;
+    if (p.k_s <= kMaxK) {  // sorted, into the sample buffers
+      m1.res_ids = w.ss_ids;
+      m1.res_scores = w.ss_sc;
+      m1.res_cnt = w.ss_cnt;
+      m1.res_slots = nullptr;
+      m1.slots = false;
+      m1.sorted = true;
+    }  // else (re-rank with a very wide k'): unsorted, into the re-rank buffers
     st = enqueue_merge(w, m1, s);
     if (st != SNN_OK) return st;
     // the select wrote each query's k_s results at stride k_s
-    HIP_TRY(this, launch_sample_thr(p.nq, p.k_s, p.k_s, w.rr_sc, w.rr_cnt, w.sthr, s), "sample threshold");
-    HIP_TRY(this, launch_fill_u32(w.keff, (uint32_t)std::min<size_t>(p.k, live), p.nq, s), "keff fill");
+    HIP_TRY(this, launch_sample_thr(p.nq, p.k_s, p.k_s, m1.res_scores, m1.res_cnt, w.sthr, s), "sample threshold");
+    HIP_TRY(this, launch_keff(p.nq, o.kq, p.k, (uint32_t)std::min<size_t>(p.k, live), w.keff, s), "keff");
     a.tiles = p.tiles;
     a.kmax = p.kt;
     a.nselect = w.stats + 2;
@@ -769,16 +784,17 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
   p.kt = std::min<uint32_t>(k, tile_docs);
-  // A wide k' (a sixteenth of a tile or more): a tile's own selection keeps the
-  // tile's k' best, a large share of it (all of it when k' reaches the tile), so
-  // a query hands the selection tiles x min(k', tile) candidates. A first pass
-  // over the first tiles / kSampleStride tiles selects the k_s best there, k_s
-  // chosen so that about 2 k' documents of the whole collection score at least
-  // the lowest of them (a slot range holds a random sample of the collection's
-  // documents; when it does not, more queries run the no-threshold pass,
-  // nothing else)
+  // A wide k (k' of Alg. 7 when re-ranking; a sixteenth of a tile or more): a
+  // tile's own selection keeps the tile's k best, a large share of it (all of
+  // it when k reaches the tile), so a query hands the selection about
+  // tiles x min(k, tile) candidates. A first pass over the first
+  // tiles / kSampleStride tiles selects the k_s best there, k_s chosen so that
+  // about 2 k documents of the whole collection score at least the lowest of
+  // them (a slot range holds a random sample of the collection's documents;
+  // when it does not, more queries run the no-threshold pass, nothing else).
+  // With per-query k the batch k sets k_s: a lower threshold is still valid.
   p.tiles_s = p.k_s = 0;
-  if (o.rerank_k != 0 && mode == SNN_MODE_BATCHED && (uint64_t)k * 16 >= tile_docs && p.tiles >= 4 * kSampleStride) {
+  if (mode == SNN_MODE_BATCHED && !o.thr_init && (uint64_t)k * 16 >= tile_docs && p.tiles >= 4 * kSampleStride) {
     const uint32_t ts = p.tiles / kSampleStride;
     const uint64_t ks = (2ull * k * ts + p.tiles - 1) / p.tiles + 32;
     if (ks < k) {
@@ -786,7 +802,8 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
       p.k_s = (uint32_t)ks;
     }
   }
-  return prepare_workspace(nq, total - o.ebase, p.kt, p.tiles, o.rerank_k ? k : 0, p.w, o.wsp ? *o.wsp : wsp, s);
+  return prepare_workspace(nq, total - o.ebase, p.kt, p.tiles, o.rerank_k ? k : 0, p.k_s, p.w, o.wsp ? *o.wsp : wsp,
+                           s);
 }
 
 snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,

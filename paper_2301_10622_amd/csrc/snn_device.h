@@ -193,6 +193,8 @@ hipError_t rerank_init();  // allows the re-rank kernel its largest LDS footprin
 
 hipError_t launch_fallback_list(uint32_t nq, const uint32_t *flags, uint32_t *qlist, uint32_t *nlist, uint32_t *thr,
                                 hipStream_t s);
+// keff[q] = min(kq ? kq[q] : kmax, cap)
+hipError_t launch_keff(uint32_t nq, const uint32_t *kq, uint32_t kmax, uint32_t cap, uint32_t *keff, hipStream_t s);
 // thr[q] = ord(lowest of the ks scores sc[q][0 .. ks)) when cnt[q] >= ks, else 0
 hipError_t launch_sample_thr(uint32_t nq, uint32_t ks, uint32_t stride, const float *sc, const uint32_t *cnt,
                              uint32_t *thr, hipStream_t s);

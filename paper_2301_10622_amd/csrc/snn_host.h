@@ -49,6 +49,8 @@ struct SearchWs {
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
   uint32_t *nz_full = nullptr;                  // [nq] whole non-zero count of each prepared query
   uint32_t *sthr = nullptr;                     // [nq] starting thresholds from a sample of the tiles
+  uint32_t *ss_ids = nullptr, *ss_cnt = nullptr;  // the sample pass's sorted selection (k_s <= 4,096)
+  float *ss_sc = nullptr;
   uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
   uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' selected candidates
   float *rr_sc = nullptr;
@@ -261,7 +263,7 @@ struct snn_index {
                                const std::vector<float> &vals, size_t r0, size_t r1);
   snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
-  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime,
+  snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime, uint32_t ksample,
                                snn::SearchWs &w, snn::Workspace &W, hipStream_t s);
   snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,

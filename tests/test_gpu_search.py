@@ -314,3 +314,52 @@ def test_autotune_keeps_results_and_reports_schedule(small):
     after = _dev_search(ix, t, 10, P.MODE_BATCHED)
     for a, b in zip(before, after):
         assert np.array_equal(a, b)
+
+
+@pytest.fixture(scope="module")
+def wide():
+    """300,000 documents of the small law: 74 tiles of 4,096 slots, enough for
+    the sampled starting thresholds of a wide k."""
+    P = _lib()
+    w = gen.make_small(5, docs=300_000, queries=16)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
+    P.load_docs(ix, w.docs)
+    yield w, ix
+    ix.close()
+
+
+@pytest.mark.parametrize("k", [256, 1000, 4096])
+def test_wide_k_sampled_thresholds_bit_identical(wide, k):
+    """k >= tile / 16 with 4,096-slot tiles starts each query from a threshold
+    found on a sample of the tiles; with 16,384-slot tiles there are too few
+    tiles to sample. Both must return the same bits, and the sampled search
+    must hand the selection a few k candidates per query (about 2 k plus the
+    sample's margin of 32, scaled to the collection), not a share of every
+    tile."""
+    w, ix = wide
+    q = w.queries
+    ix.set_schedule(16, 16, 2048, True)
+    got = ix.search_batch(q.indptr, q.coords, q.vals, k)
+    work = ix.last_batch_work()
+    _, fallbacks = ix.last_batch_status()
+    ix.set_schedule(16, 64, 2048, True)
+    ref = ix.search_batch(q.indptr, q.coords, q.vals, k)
+    ix.set_schedule(16, 16, 2048, True)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b), k
+    assert fallbacks == 0
+    assert 0 < work["candidates"] < q.rows * 8 * k, work
+
+
+def test_wide_k_sampled_thresholds_match_oracle(wide):
+    w, ix = wide
+    P = _lib()
+    q = w.queries.take(range(4))
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    ids, sc, cnt = ix.search_batch(q.indptr, q.coords, q.vals, 1000)
+    pos_of_id = {i: i for i in range(w.docs.rows)}
+    for qi in range(q.rows):
+        s, a = ora.score_all(*q.row(qi))
+        c = int(cnt[qi])
+        parity.check_query(ids[qi][:c], sc[qi][:c], s, a, pos_of_id, np.arange(w.docs.rows), 1000,
+                           what="wide k q%d" % qi)

@@ -144,3 +144,32 @@ def test_serving_rejects_malformed_traces_without_changes():
                      np.ones(int(ip[-1]), np.float32))
         assert ex.value.status == -1
     assert ix.live_count == before
+
+
+def test_serving_wide_k_uses_sampled_thresholds_and_keeps_results():
+    """A 300,000-document index (74 tiles): batches with k up to 1,000 start
+    from sampled thresholds; each search returns the bits of the same search
+    run alone in a batch of its k on a schedule too coarse to sample."""
+    import paper_2301_10622_amd as P
+
+    docs = gen.small_docs(4, 300_000)
+    ix = P.Index(1000, 32, 1, capacity=300_000, hash_seed=4)
+    P.load_docs(ix, docs)
+    tr = gen.serving_trace(5, 240, np.arange(docs.rows), docs.rows, 1e9, frac_query=1.0, frac_insert=0.0,
+                           ks=(10, 100, 1000))
+    csr = gen.trace_csr(tr)
+    ix.set_schedule(16, 16, 2048, True)
+    res_ids, res_sc, res_cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords,
+                                                  csr.vals, max_batch=64, max_inflight=3, streams=3, realtime=False,
+                                                  budget_bytes=8 << 30)
+    assert rep["searches"] == 240 and rep["rejected"] == 0
+    ix.set_schedule(16, 64, 2048, True)
+    for k in (10, 100, 1000):
+        sel = np.nonzero(tr["k"] == k)[0]
+        qs = csr.take(sel.tolist())
+        ids, sc, cnt = ix.search_batch(qs.indptr, qs.coords, qs.vals, k)
+        for j, r in enumerate(sel):
+            c = int(res_cnt[r])
+            assert c == int(cnt[j]) and np.array_equal(res_ids[r][:c], ids[j][:c]), (k, r)
+            assert np.array_equal(res_sc[r][:c], sc[j][:c]), (k, r)
+    ix.close()
