@@ -385,22 +385,35 @@ def tile_kernel_name(sched, form):
     return ("k_tiles_persistent<%d>" if sched["persistent"] else "k_tiles<%d>") % R
 
 
+def kernel_source_sha256():
+    """Fingerprint of the scoring kernel's sources (kernels_search.hip and
+    snn_device.h) with comments and blank lines left out, so that a comment
+    edit does not orphan the counters taken for the same code."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for f in ("paper_2301_10622_amd/csrc/kernels_search.hip", "paper_2301_10622_amd/csrc/snn_device.h"):
+        text = open(os.path.join(ROOT, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for line in text.splitlines():
+            line = line.split("//", 1)[0].rstrip()
+            if line:
+                h.update(line.encode() + b"\n")
+    return h.hexdigest()
+
+
 def measured_traffic(kernel, k):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     passes (calibrated against a plain copy), or None when the kernel source has
     changed since they were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
-    h = hashlib.sha256()
-    for f in ("paper_2301_10622_amd/csrc/kernels_search.hip", "paper_2301_10622_amd/csrc/snn_device.h"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
+    if kernel_source_sha256() != rec["source_sha256"]:
         return None
     if k == 100 and "k100" in rec:
         return rec["k100"]["traffic_bytes_per_launch"]

@@ -559,10 +559,12 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
 }
 
 // Enqueue one batched or plain search. The device work is: query preparation,
-// threshold initialisation, the scoring + selection tiles, the merge levels.
-// A learned-filter pass first predicts each query's threshold (features, MLP),
-// and after the filtered merge runs the plain tiles and merge again for the
-// queries that kept fewer than min(k, live) candidates, all on the device.
+// threshold initialisation, the scoring + selection tiles, the select of each
+// query's top-k over its tiles, and with k' > k the exact re-rank and the final
+// select. Starting thresholds come from a learned-filter pass (features, MLP)
+// or, for a wide k, from a first pass over a sample of the tiles; the queries
+// that then kept fewer than min(k, live) candidates run the tiles and select
+// again without one, all on the device.
 // ev (nullable): events around the tile launches (main pass, fallback pass).
 snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t *ev) {
   const SearchWs &w = p.w;

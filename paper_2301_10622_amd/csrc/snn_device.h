@@ -38,7 +38,6 @@ namespace snn {
 constexpr int kWaves = 4;               // waves per workgroup
 constexpr int kBlock = 64 * kWaves;      // threads per workgroup
 constexpr uint32_t kTileMax = 16384;     // largest tile (docs); capacity is a multiple
-constexpr int kMergeCap = 8192;          // candidates one merge workgroup sorts in LDS
 constexpr int kPrepCap = 4096;           // max non-zeros of one query
 constexpr uint32_t kMaxK = 4096;        // largest k of a sorted result
 constexpr uint32_t kMaxKPrime = 65536;  // largest k' of the re-rank (Alg. 7)
