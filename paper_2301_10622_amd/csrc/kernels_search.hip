@@ -526,6 +526,72 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
   }
 }
 
+// One query alone (the plain form): its 256 R-slot tiles fill only part of the
+// device, so the time of a tile is the length of its chain of memory round
+// trips, not throughput. This body keeps a whole chunk in flight at once: the
+// bounds of the chunk's PC entries are loaded together, with the posting bits
+// of the next chunk, and then applied in entry order (the same terms, added in
+// the same order as tile_body). h = 1 only; registers are plentiful here.
+template <int R, bool kBf16>
+__device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
+  constexpr int G = R / 4;
+  constexpr int PC = 4;  // entries per chunk
+  using LB = typename LaneBits<G>::type;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wslot0 = t * (uint32_t)(kBlock * R) + (uint32_t)wave * 256u * G;
+  const DevIndex &ix = a.ix;
+  if (as_const(a.qd.status)[q] != 0u) {  // malformed query: no candidates
+    if (threadIdx.x == 0) a.cand_cnt[(size_t)q * a.tiles + t] = 0;
+    return;
+  }
+  float acc[R];
+#pragma unroll
+  for (int x = 0; x < R; ++x) acc[x] = 0.0f;
+  const uint64_t e0 = as_const(a.qd.qptr)[q] - a.qd.ebase;
+  const uint32_t ne = as_const(a.qd.cnt)[q];
+  const cptr<uint32_t> qj = as_const(a.qd.j);
+  const cptr<float> qq = as_const(a.qd.q);
+  const cptr<uint32_t> qb = as_const(a.qd.b);
+  LB cb[PC];
+#pragma unroll
+  for (int k = 0; k < PC; ++k) cb[k] = ne ? lane_bits<G>(ix, qj[e0 + min((uint32_t)k, ne - 1u)], wslot0, lane) : (LB)0;
+  for (uint32_t c0 = 0; c0 < ne; c0 += PC) {
+    LB nb[PC];
+    const bool more = c0 + PC < ne;
+#pragma unroll
+    for (int k = 0; k < PC; ++k)
+      nb[k] = more ? lane_bits<G>(ix, qj[e0 + min(c0 + PC + (uint32_t)k, ne - 1u)], wslot0, lane) : (LB)0;
+    float v[PC][G][4];
+    uint32_t qbits[PC];
+#pragma unroll
+    for (int k = 0; k < PC; ++k) {
+      const uint32_t c = min(c0 + (uint32_t)k, ne - 1u);  // past the end: a repeat with no bits
+      const LB bk = c0 + (uint32_t)k < ne ? cb[k] : (LB)0;
+      cb[k] = bk;
+      const float qv = qq[e0 + c];
+      qbits[k] = __builtin_bit_cast(uint32_t, qv);
+      const __amdgpu_buffer_rsrc_t rs = row_rsrc<kBf16, G>(ix, qv > 0.0f, qb[e0 + c] >> 1, wslot0);
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+        load4<kBf16>(rs, group_bits(bk, r) ? r * Elem<kBf16>::kGroup + lane * Elem<kBf16>::kLane : kOob, v[k][r]);
+    }
+    // every load of the chunk is issued before the first add (the scheduler
+    // would otherwise trade this overlap for registers)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < PC; ++k)
+#pragma unroll
+      for (int r = 0; r < G; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          acc[4 * r + i] = __builtin_fmaf(masked_q(cb[k], 4 * r + i, qbits[k]), v[k][r][i], acc[4 * r + i]);
+#pragma unroll
+    for (int k = 0; k < PC; ++k) cb[k] = nb[k];
+  }
+  finish<R>(a, q, t, acc, sh);
+}
+
 template <int R, bool kBf16>
 __device__ __forceinline__ void one_item(const TileArgs &a, SelShared &sh) {
   uint32_t q = a.q0 + blockIdx.y;
@@ -546,6 +612,15 @@ template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles_bf16(TileArgs a) {
   __shared__ SelShared sh;
   one_item<R, true>(a, sh);
+}
+
+// the plain form: query a.q0 alone, one workgroup per tile (R = 64 keeps the
+// throughput body: a chunk of its bounds would not fit the registers)
+template <int R, bool kBf16>
+__global__ __launch_bounds__(kBlock) void k_tiles_latency(TileArgs a) {
+  __shared__ SelShared sh;
+  if (R <= 32 && a.ix.h == 1) tile_body_latency<R, kBf16>(a, a.q0, blockIdx.x, sh);
+  else tile_body<R, kBf16>(a, a.q0, blockIdx.x, sh);
 }
 
 // Persistent form: a fixed grid pulls (query, tile) items from per-XCD queues.
@@ -662,6 +737,23 @@ hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_
     case 16: hipLaunchKernelGGL(bf ? k_tiles_bf16<16> : k_tiles<16>, grid, dim3(kBlock), 0, s, a); break;
     case 32: hipLaunchKernelGGL(bf ? k_tiles_bf16<32> : k_tiles<32>, grid, dim3(kBlock), 0, s, a); break;
     case 64: hipLaunchKernelGGL(bf ? k_tiles_bf16<64> : k_tiles<64>, grid, dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int R>
+static void launch_latency_r(const TileArgs &a, bool bf, hipStream_t s) {
+  if (bf) hipLaunchKernelGGL((k_tiles_latency<R, true>), dim3(a.tiles), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_tiles_latency<R, false>), dim3(a.tiles), dim3(kBlock), 0, s, a);
+}
+
+hipError_t launch_tiles_latency(const TileArgs &a, int R, hipStream_t s) {
+  const bool bf = (a.ix.flags & kSketchBf16) != 0;
+  switch (R) {
+    case 16: launch_latency_r<16>(a, bf, s); break;
+    case 32: launch_latency_r<32>(a, bf, s); break;
+    case 64: launch_latency_r<64>(a, bf, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

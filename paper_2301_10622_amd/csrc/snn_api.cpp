@@ -617,7 +617,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
       a.q0 = q;
       hipEvent_t e0 = prof_on ? prof_event() : nullptr;
       if (e0) HIP_TRY(this, hipEventRecord(e0, s), "event");
-      HIP_TRY(this, launch_tiles(a, p.R, 1, s), "tile kernel");
+      HIP_TRY(this, launch_tiles_latency(a, p.R, s), "tile kernel");
       if (e0) {
         hipEvent_t e1 = prof_event();
         HIP_TRY(this, hipEventRecord(e1, s), "event");

@@ -164,6 +164,8 @@ hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);
+// one query (a.q0) alone, latency-first (the plain form)
+hipError_t launch_tiles_latency(const TileArgs &a, int R, hipStream_t s);
 hipError_t launch_tiles_persistent(const TileArgs &a, int R, uint32_t grid, hipStream_t s);
 // h = 1: Q queries per workgroup, one sketch-row load for all of them; the
 // non-persistent form launches (tiles, ng_launch) groups from group a.q0
