@@ -108,3 +108,32 @@ def test_upper_only_bf16_matches_oracle_and_rejects_negatives():
     assert int(cnt[0]) == 0 and int(cnt[1]) == 5
     assert ix.last_batch_status()[0] == 1
     ix.close()
+
+
+@pytest.mark.parametrize("bf16,upper", [(True, False), (False, True), (True, True)])
+def test_sketch_variants_every_schedule_same_bits(bf16, upper):
+    """The bfloat16 and upper-only sketches under every batched schedule (one,
+    two and three queries per workgroup; R = 8 .. 64; persistent or not): the
+    same bits as the plain form, and the bfloat16 results against its oracle."""
+    P = _P()
+    if upper:
+        docs, qs = _nonneg(41, docs=30011, queries=24)
+        n, m = 3000, 64
+    else:
+        rng = np.random.default_rng(7)
+        docs = gen.sparse_rows(43, 30011, 1500, 1.1, rng.integers(1, 70, 30011), "normal")
+        qs = gen.sparse_rows(44, 24, 1500, 1.1, rng.integers(1, 50, 24), "normal")
+        n, m = 1500, 24
+    ix = P.Index(n, m, 1, capacity=30011, hash_seed=11, sketch_bf16=bf16, upper_only=upper)
+    P.load_docs(ix, docs)
+    ref = ix.search_ex(qs.indptr, qs.coords, qs.vals, 10, mode=P.MODE_PLAIN)
+    for R, Q in ((16, 1), (32, 1), (64, 1), (16, 2), (16, 3), (8, 2), (8, 4)):
+        for persistent in (True, False):
+            ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=2048, persistent=persistent, qgroup=Q)
+            got = ix.search_ex(qs.indptr, qs.coords, qs.vals, 10, mode=P.MODE_BATCHED)
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), (R, Q, persistent)
+    if bf16:
+        ora = O.Index(docs, n, m, 1, 11, bf16=True)
+        parity.check_batch(ref[0], ref[1], ref[2], ora, qs, 10, what="bf16 upper=%s" % upper)
+    ix.close()
