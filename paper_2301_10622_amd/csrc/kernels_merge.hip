@@ -31,6 +31,7 @@ __device__ __forceinline__ cptr<T> as_const(const T *p) {
 constexpr int kSelBlock = 512;
 constexpr int kSelWaves = kSelBlock / 64;
 constexpr int kSelBins = 4096;
+constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
 
 template <bool kPay, bool kSorted>
 __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
@@ -39,6 +40,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   __shared__ uint64_t sel[kSorted ? kMaxK : 1];
   __shared__ uint32_t sels[kPay && kSorted ? kMaxK : 1];
   __shared__ uint32_t sh_bin, sh_need, sh_pos;
+  __shared__ uint32_t goff[kSelScanMax + 1];  // first key of each group among all the query's keys
   uint32_t q = a.q0 + blockIdx.y;
   if (a.qlist) {
     if (q >= *as_const(a.nlist)) return;
@@ -50,25 +52,60 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   const uint64_t *base = a.in + (size_t)q * G * a.in_stride;
   const uint32_t kq = a.kq ? as_const(a.kq)[q] : a.kmax;
   const bool bad = a.status && a.status[q] != 0u;
-  // every key of the query: wave w walks groups w, w + 8, ..., its lanes the group's keys
-  auto for_each = [&](auto f) {
-    for (uint32_t g = (uint32_t)wave; g < G; g += kSelWaves) {
-      const uint32_t c = cnts[g];
-      const uint64_t *src = base + (size_t)g * a.in_stride;
-      for (uint32_t e = (uint32_t)lane; e < c; e += 64) f(src[e], g, e);
-    }
-  };
-  // M = number of candidates
+  // M = number of candidates; with at most kSelScanMax groups also each
+  // group's first key in the concatenation of all groups (thread t sums the
+  // groups t * per .. t * per + per - 1, then a scan over the threads)
+  const bool scan = G <= kSelScanMax;
+  const uint32_t gper = (G + kSelBlock - 1) / kSelBlock;
   uint32_t mine = 0;
-  for (uint32_t g = (uint32_t)tid; g < G; g += kSelBlock) mine += cnts[g];
+  if (scan) {
+    for (uint32_t g = (uint32_t)tid * gper; g < min(G, ((uint32_t)tid + 1) * gper); ++g) mine += cnts[g];
+  } else {
+    for (uint32_t g = (uint32_t)tid; g < G; g += kSelBlock) mine += cnts[g];
+  }
   part[tid] = mine;
   __syncthreads();
-  for (int d = kSelBlock / 2; d > 0; d >>= 1) {
-    if (tid < d) part[tid] += part[tid + d];
+  for (int off = 1; off < kSelBlock; off <<= 1) {  // inclusive scan
+    const uint32_t v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
     __syncthreads();
   }
-  const uint32_t M = part[0];
+  const uint32_t M = part[kSelBlock - 1];
+  if (scan) {
+    uint32_t o = part[tid] - mine;
+    for (uint32_t g = (uint32_t)tid * gper; g < min(G, ((uint32_t)tid + 1) * gper); ++g) {
+      goff[g] = o;
+      o += cnts[g];
+    }
+    if (tid == 0) goff[G] = M;
+  }
   __syncthreads();
+  // Every key of the query. Small groups (fewer than 64 keys on average): the
+  // threads stride over the concatenated keys and find each key's group by
+  // binary search in goff, so no lane idles on a short group; otherwise wave w
+  // walks groups w, w + 8, ..., its lanes the group's keys.
+  const bool flat = scan && M < 64u * G;
+  auto for_each = [&](auto f) {
+    if (flat) {
+      for (uint32_t i = (uint32_t)tid; i < M; i += kSelBlock) {
+        uint32_t lo = 0, hi = G;  // goff[lo] <= i < goff[hi]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (goff[mid] <= i) lo = mid;
+          else hi = mid;
+        }
+        const uint32_t e = i - goff[lo];
+        f(base[(size_t)lo * a.in_stride + e], lo, e);
+      }
+    } else {
+      for (uint32_t g = (uint32_t)wave; g < G; g += kSelWaves) {
+        const uint32_t c = cnts[g];
+        const uint64_t *src = base + (size_t)g * a.in_stride;
+        for (uint32_t e = (uint32_t)lane; e < c; e += 64) f(src[e], g, e);
+      }
+    }
+  };
   if (a.emitted && tid == 0 && M) atomicAdd(a.emitted, (unsigned long long)M);
   const uint32_t keep = bad ? 0u : min(M, kq);
   uint64_t T = 0;  // the result is every key >= T
