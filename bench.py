@@ -489,6 +489,10 @@ def paper_gaussian(args, dev, P, gen, np, torch, psi):
                         q.rows))
     res = {"workload": w.name, "docs": w.docs.rows, "dim": w.n, "m": w.m, "queries": nq, "k": k, "k_prime": kp,
            "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1), "forms": {}}
+    # the batched schedule, tuned on the first batch at k = 1,000
+    ip0, qc0, qv0, _ = batches[0]
+    res["schedule"] = ix.autotune(ip0, qc0, qv0, k, total=int(qc0.numel()))
+    log("g%d: schedule %s" % (psi, res["schedule"]))
     outs = {}
     budgets = (0, 50, 25) if psi == 100 else (0, 100, 50)
     for c in budgets:
