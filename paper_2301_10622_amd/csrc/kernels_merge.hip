@@ -88,21 +88,45 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   const bool flat = scan && M < 64u * G;
   auto for_each = [&](auto f) {
     if (flat) {
-      for (uint32_t i = (uint32_t)tid; i < M; i += kSelBlock) {
-        uint32_t lo = 0, hi = G;  // goff[lo] <= i < goff[hi]
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (goff[mid] <= i) lo = mid;
-          else hi = mid;
+      constexpr int U = 4;  // keys in flight per thread
+      for (uint32_t i0 = (uint32_t)tid; i0 < M; i0 += U * kSelBlock) {
+        uint64_t kk[U];
+        uint32_t gg[U], ee[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t i = i0 + (uint32_t)u * kSelBlock;
+          gg[u] = ee[u] = 0;
+          kk[u] = 0;
+          if (i < M) {
+            uint32_t lo = 0, hi = G;  // goff[lo] <= i < goff[hi]
+            while (hi - lo > 1) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (goff[mid] <= i) lo = mid;
+              else hi = mid;
+            }
+            gg[u] = lo;
+            ee[u] = i - goff[lo];
+            kk[u] = base[(size_t)lo * a.in_stride + ee[u]];
+          }
         }
-        const uint32_t e = i - goff[lo];
-        f(base[(size_t)lo * a.in_stride + e], lo, e);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (i0 + (uint32_t)u * kSelBlock < M) f(kk[u], gg[u], ee[u]);
       }
     } else {
-      for (uint32_t g = (uint32_t)wave; g < G; g += kSelWaves) {
-        const uint32_t c = cnts[g];
-        const uint64_t *src = base + (size_t)g * a.in_stride;
-        for (uint32_t e = (uint32_t)lane; e < c; e += 64) f(src[e], g, e);
+      // two groups at a time, so two groups' keys are in flight per lane
+      for (uint32_t g = (uint32_t)wave; g < G; g += 2 * kSelWaves) {
+        const uint32_t g2 = g + kSelWaves;
+        const uint32_t c1 = scan ? goff[g + 1] - goff[g] : cnts[g];
+        const uint32_t c2 = g2 < G ? (scan ? goff[g2 + 1] - goff[g2] : cnts[g2]) : 0u;
+        const uint64_t *s1 = base + (size_t)g * a.in_stride;
+        const uint64_t *s2 = base + (size_t)g2 * a.in_stride;
+        for (uint32_t e = (uint32_t)lane; e < max(c1, c2); e += 64) {
+          const uint64_t k1 = e < c1 ? s1[e] : 0ull;
+          const uint64_t k2 = e < c2 ? s2[e] : 0ull;
+          if (e < c1) f(k1, g, e);
+          if (e < c2) f(k2, g2, e);
+        }
       }
     }
   };
