@@ -22,6 +22,7 @@
 namespace snn {
 
 constexpr int kRrWaves = 8;
+constexpr int kRrStep = 8;  // candidates a wave scores at once
 constexpr int kRrBlock = 64 * kRrWaves;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // no coordinate reaches 2^31
 
@@ -88,19 +89,39 @@ __global__ __launch_bounds__(kRrBlock) void k_rerank(RerankArgs a) {
       len = a.fw.len[slot];
     }
     const uint32_t here = min(64u, hi - base);
-    for (uint32_t t = 0; t < here; ++t) {
-      const uint64_t o = ((uint64_t)shfl_u32((uint32_t)(off >> 32), (int)t) << 32) | shfl_u32((uint32_t)off, (int)t);
-      const uint32_t ln = shfl_u32(len, (int)t);
-      float acc = 0.0f;
-      for (uint32_t e = (uint32_t)lane; e < ln; e += 64u) {
-        const uint2 en = a.fw.ent[o + e];
-        acc = __builtin_fmaf(lookup(en.x), __builtin_bit_cast(float, en.y), acc);
+    // kRrStep candidates at a time, so their entries' loads are in flight
+    // together; each candidate's sum is formed exactly as alone (lane l adds
+    // entries l, l + 64, ... in order, then the butterfly)
+    for (uint32_t t0 = 0; t0 < here; t0 += kRrStep) {
+      uint64_t o[kRrStep];
+      uint32_t ln[kRrStep];
+      float acc[kRrStep];
+      uint32_t lmax = 0;
+#pragma unroll
+      for (int u = 0; u < kRrStep; ++u) {
+        const uint32_t t = t0 + (uint32_t)u;
+        const int src = t < here ? (int)t : 0;
+        o[u] = ((uint64_t)shfl_u32((uint32_t)(off >> 32), src) << 32) | shfl_u32((uint32_t)off, src);
+        ln[u] = t < here ? shfl_u32(len, src) : 0u;
+        lmax = max(lmax, ln[u]);
+        acc[u] = 0.0f;
+      }
+      for (uint32_t e = (uint32_t)lane; e < lmax; e += 64u) {
+        uint2 en[kRrStep];
+#pragma unroll
+        for (int u = 0; u < kRrStep; ++u) en[u] = e < ln[u] ? a.fw.ent[o[u] + e] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < kRrStep; ++u)
+          if (e < ln[u]) acc[u] = __builtin_fmaf(lookup(en[u].x), __builtin_bit_cast(float, en[u].y), acc[u]);
       }
 #pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-      if ((uint32_t)lane == t) {
-        const float s = acc == 0.0f ? 0.0f : acc;  // -0 -> +0
-        a.keys[cbase + c] = ((uint64_t)ord_key(s) << 32) | (uint64_t)(0xFFFFFFFFu - id);
+      for (int u = 0; u < kRrStep; ++u) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc[u] += __shfl_xor(acc[u], d, 64);
+        if ((uint32_t)lane == t0 + (uint32_t)u && t0 + (uint32_t)u < here) {
+          const float s = acc[u] == 0.0f ? 0.0f : acc[u];  // -0 -> +0
+          a.keys[cbase + c] = ((uint64_t)ord_key(s) << 32) | (uint64_t)(0xFFFFFFFFu - id);
+        }
       }
     }
   }
