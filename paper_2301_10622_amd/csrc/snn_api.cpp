@@ -850,6 +850,8 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
   key.cslot = W.cslot.p;
   key.rr = W.rr.p;
   key.fwd = fw.ent;
+  // the sampled pass's required counts, min(k, live), are kernel arguments
+  key.skeff = p.tiles_s ? (uint32_t)std::min<size_t>(k, live) : 0u;
   if (const LearnedPass *lp = o.learned) {
     key.lX = lp->X; key.ly = lp->yhat; key.lthr = lp->thr; key.lkeff = lp->keff; key.lPb = lp->Pb;
     key.ltab = lp->table; key.lkeff_v = lp->keff_value;

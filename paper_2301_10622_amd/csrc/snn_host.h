@@ -141,6 +141,7 @@ struct GraphKey {
   const void *ptr, *c, *v, *ids, *sc, *cnt, *thr, *kq, *keff, *ws, *cand, *qseq;
   const void *lX, *ly, *lthr, *lkeff, *lPb, *ltab;
   uint32_t ldelta, lkeff_v, rerank_k, hash_cap, max_coords;
+  uint32_t skeff;  // sampled starting thresholds: the count cap min(k, live) the graph holds (0: none)
   const void *cslot, *rr, *fwd;
   uint64_t ebase;
   hipStream_t stream;
@@ -149,7 +150,7 @@ struct GraphKey {
            qgroup == o.qgroup &&
            lX == o.lX && ly == o.ly && lthr == o.lthr && lkeff == o.lkeff && lPb == o.lPb && ltab == o.ltab &&
            ldelta == o.ldelta && lkeff_v == o.lkeff_v && rerank_k == o.rerank_k && hash_cap == o.hash_cap &&
-           max_coords == o.max_coords &&
+           max_coords == o.max_coords && skeff == o.skeff &&
            cslot == o.cslot && rr == o.rr && fwd == o.fwd &&
            total == o.total && persistent == o.persistent && prof == o.prof && ptr == o.ptr && c == o.c &&
            v == o.v && ids == o.ids && sc == o.sc && cnt == o.cnt && thr == o.thr && kq == o.kq && keff == o.keff &&

@@ -363,3 +363,36 @@ def test_wide_k_sampled_thresholds_match_oracle(wide):
         c = int(cnt[qi])
         parity.check_query(ids[qi][:c], sc[qi][:c], s, a, pos_of_id, np.arange(w.docs.rows), 1000,
                            what="wide k q%d" % qi)
+
+
+def test_sampled_thresholds_graph_replays_follow_the_live_count():
+    """A wide k on a collection with many tiles but few live documents (most
+    deleted): the sampled pass's required count is min(k, live), a value the
+    captured graph holds, so inserts into freed slots (same tile count) must
+    lead to a new graph. Each replay equals the eager plain path."""
+    import torch
+
+    P = _lib()
+    w = gen.make_small(6, docs=270_000, queries=8)
+    stream = torch.cuda.Stream()  # a capturable (non-default) stream, default priority
+    torch.cuda.set_stream(stream)
+    ix = P.Index(w.n, w.m, w.h, capacity=270_000, hash_seed=w.hash_seed, stream=stream)
+    P.load_docs(ix, w.docs)
+    ix.delete_batch(np.arange(3000, 270_000))
+    t = _dev_batch(w.queries)
+    dev = torch.device("cuda:0")
+    k = 4000
+    out = (torch.empty((8, k), dtype=torch.int32, device=dev), torch.empty((8, k), dtype=torch.float32, device=dev),
+           torch.empty(8, dtype=torch.int32, device=dev))
+    extra = gen.small_docs(77, 6000)
+    for it in range(3):
+        got = _dev_search(ix, t, k, P.MODE_BATCHED, out=out)
+        ref = _dev_search(ix, t, k, P.MODE_PLAIN)
+        assert np.all(got[2] == min(k, ix.live_count)), (it, got[2], ix.live_count)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), it
+        sub = extra.take(range(it * 2000, it * 2000 + 2000))
+        ix.insert_batch(np.arange(2000) + 1_000_000 + it * 2000, sub.indptr, sub.coords, sub.vals)
+    torch.cuda.synchronize()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    ix.close()
