@@ -670,8 +670,11 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     keff = lp->keff;
   } else if (p.tiles_s) {
     HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
+    // one k for every query here: a tile keeps at most kmax candidates per
+    // query (the stride of this pass), whatever the query's own k
     a.tiles = p.tiles_s;
     a.kmax = std::min(p.k_s, p.kt);
+    a.kq = nullptr;
     a.nselect = nullptr;
     st = tiles_pass(nullptr, nullptr);
     if (st != SNN_OK) return st;
@@ -699,6 +702,7 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     HIP_TRY(this, launch_keff(p.nq, o.kq, p.k, (uint32_t)std::min<size_t>(p.k, live), w.keff, s), "keff");
     a.tiles = p.tiles;
     a.kmax = p.kt;
+    a.kq = o.kq;
     a.nselect = w.stats + 2;
     thr_init = w.sthr;
     keff = w.keff;
