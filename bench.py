@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--serving-ops", type=int, default=100_000)
     ap.add_argument("--plain-steps", type=int, default=3)
     ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--updates", type=int, default=131072,
+                    help="documents deleted and re-inserted to time the update kernels (0: build only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: run one plain device copy of this size first (counter calibration)")
@@ -96,11 +98,15 @@ def main():
     # the Sinnamon search itself never reads it
     ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream, forward_store=True)
     torch.cuda.synchronize()
+    ix.profile(True)
     t = time.time()
     P.load_docs(ix, w.docs)
     torch.cuda.synchronize()
     t_ins = time.time() - t
-    log("index built: %.2fs (%.0f docs/s through the host API)" % (t_ins, w.docs.rows / t_ins))
+    build_upd = ix.profile_read_updates()
+    ix.profile(False)
+    log("index built: %.2fs (%.0f docs/s through the host API; insert kernel %.2f ms for %d docs)" % (
+        t_ins, w.docs.rows / t_ins, build_upd["insert_ms"], build_upd["insert_docs"]))
 
     # algorithmic bytes per query: every posting of a query coordinate costs its
     # 4-byte id and h 4-byte sketch values; plus 12 B per query entry and 8 B per result
@@ -205,6 +211,11 @@ def main():
         log("rerank   k=%d k'=%-5d coords %-4s %8.3f ms/step  %10.0f q/s" % (args.k, kp, c or "all", ms,
                                                                           nq / (ms / 1000.0)))
 
+    # update kernels (Alg. 5 insert, Section 4.3 delete), timed with HIP events
+    # around each launch: the 1M-doc build into fresh slots above, then a delete
+    # and re-insert of the first 131,072 documents into the freed slots
+    updates = update_kernels(P, np, ix, w, build_upd, args.updates)
+
     # memory levers: the same collection with a bfloat16 and / or upper-only sketch
     variants_res = {}
     if not args.no_variants:
@@ -265,6 +276,7 @@ def main():
         "roofline": roofline,
         "forms": {n: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()} for n, r in forms.items()},
         "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1),
+        "update_kernels": updates,
         "schedule": sched,
         "filters": filters,
     }
@@ -350,6 +362,45 @@ def main():
     if not args.no_serving:
         result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
     print(json.dumps(result), flush=True)
+
+
+def update_kernels(P, np, ix, w, build, n_upd):
+    """Docs/s and algorithmic GB/s of the insert and delete kernels.
+
+    Algorithmic bytes per document (Alg. 5 / Section 4.3): insert reads its
+    psi_d (coordinate, value) pairs (8 B each), writes the 2m-entry sketch
+    column (4 B each), appends the slot to psi_d lists (4 B each) and, with the
+    forward store, copies the pairs there (8 B each); delete reads the psi_d
+    stored coordinates (4 B each) and removes the slot from psi_d lists (4 B
+    each)."""
+    nnz = np.diff(w.docs.indptr)
+    two_m = 2 * w.m
+    res = {}
+
+    def line(tag, ms, docs, nbytes):
+        r = {"docs": int(docs), "kernel_ms": round(ms, 3), "docs_per_s": round(docs / (ms / 1000.0), 1),
+             "alg_GBps": round(nbytes / (ms / 1000.0) / 1e9, 1),
+             "hbm_frac": round(nbytes / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)}
+        log("%-14s %8d docs  %8.3f ms  %12.0f docs/s  alg %7.1f GB/s (%.1f%% of HBM peak)" % (
+            tag, docs, ms, r["docs_per_s"], r["alg_GBps"], 100 * r["hbm_frac"]))
+        return r
+
+    ins_bytes = lambda psi: float(np.sum(8 * psi + 4 * two_m + 4 * psi + 8 * psi))
+    res["insert_build"] = line("insert build", build["insert_ms"], build["insert_docs"], ins_bytes(nnz))
+    if n_upd > 0:
+        n_upd = min(n_upd, w.docs.rows)
+        ids = np.arange(n_upd, dtype=np.uint32)
+        sub = w.docs.take(range(n_upd))
+        ix.profile(True)
+        ix.delete_batch(ids)
+        P.load_docs(ix, sub, ids=ids)
+        u = ix.profile_read_updates()
+        ix.profile(False)
+        psi = nnz[:n_upd]
+        res["delete"] = line("delete", u["delete_ms"], u["delete_docs"], float(np.sum(8 * psi)))
+        res["insert_reuse"] = line("insert reuse", u["insert_ms"], u["insert_docs"], ins_bytes(psi))
+    res["bytes_per_doc"] = "insert 20 psi_d + 8m (forward store on), delete 8 psi_d"
+    return res
 
 
 def measured_copy_gbps(torch, dev, mib=1024, reps=10):

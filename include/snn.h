@@ -390,6 +390,16 @@ snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l);
 snn_status snn_profile_enable(snn_index *ix, int on);
 snn_status snn_profile_read(snn_index *ix, double *tile_ms, uint32_t *launches);
 
+/* Update-kernel timing (Alg. 5 insert, Section 4.3 delete). While profiling is
+ * enabled, every launch of the insert kernel and of the delete kernel made by
+ * snn_insert_batch / snn_delete_batch (and the single forms) is bracketed by
+ * HIP events on the index's stream. This call synchronises them and returns,
+ * per kernel, the summed time in milliseconds and the documents the launches
+ * covered since the previous read (then resets both). Host validation and
+ * the upload are outside the brackets. Any output pointer may be NULL. */
+snn_status snn_profile_read_updates(snn_index *ix, double *insert_ms, uint64_t *insert_docs, double *delete_ms,
+                                    uint64_t *delete_docs);
+
 size_t snn_live_count(const snn_index *ix);
 const char *snn_last_error(const snn_index *ix); /* never NULL */
 

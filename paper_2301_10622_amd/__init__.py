@@ -36,7 +36,7 @@ EXPORTS = [
     "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_search_ex", "snn_search_ex_dev",
                      "snn_bucket_table",
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
-    "snn_autotune", "snn_get_schedule", "snn_set_schedule",
+    "snn_profile_read_updates", "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
     "snn_filter_set_params", "snn_filter_set_delta", "snn_mlp_loss_grad", "snn_serve_run",
 ]
@@ -145,6 +145,7 @@ def lib():
         L.snn_read_sketch.argtypes = [P, u32, P, P]
         L.snn_profile_enable.argtypes = [P, i32]
         L.snn_profile_read.argtypes = [P, P, P]
+        L.snn_profile_read_updates.argtypes = [P, P, P, P, P]
         L.snn_autotune.argtypes = [P, u32, P, u64, P, P, u32, P]
         L.snn_get_schedule.argtypes = [P, P]
         L.snn_set_schedule.argtypes = [P, P]
@@ -164,7 +165,7 @@ def lib():
                      "snn_search_batch", "snn_search_batch_dev", "snn_last_batch_status",
                      "snn_last_batch_work", "snn_search_rerank", "snn_search_rerank_dev", "snn_search_ex", "snn_search_ex_dev",
     "snn_bucket_table",
-                     "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_autotune",
+                     "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_profile_read_updates", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
                      "snn_mlp_loss_grad", "snn_serve_run"):
@@ -377,6 +378,17 @@ class Index:
         n = ctypes.c_uint32()
         self._check(lib().snn_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+    def profile_read_updates(self):
+        """{insert_ms, insert_docs, delete_ms, delete_docs}: summed kernel time of
+        the insert and delete kernels and the documents they covered since the
+        last read."""
+        ims, dms = ctypes.c_double(), ctypes.c_double()
+        idocs, ddocs = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(lib().snn_profile_read_updates(self._h, ctypes.byref(ims), ctypes.byref(idocs),
+                                                   ctypes.byref(dms), ctypes.byref(ddocs)))
+        return {"insert_ms": float(ims.value), "insert_docs": int(idocs.value),
+                "delete_ms": float(dms.value), "delete_docs": int(ddocs.value)}
 
     # ------------------------------------------------------------- schedule
     def autotune(self, indptr, coords, vals, k: int, total: Optional[int] = None) -> dict:

@@ -3,11 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -106,40 +108,79 @@ snn_status snn_index::hip_fail(hipError_t e, const char *what) {
   } while (0)
 
 // Validate one sparse vector; appends its non-zero entries to out_c/out_v.
-bool snn_check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v, std::vector<uint32_t> &oc,
-                         std::vector<float> &ov, std::vector<uint32_t> &scratch, const char *what) {
-  if (nnz && (!c || !v)) {
-    ix->fail(SNN_E_INVALID, "%s: null coordinate or value pointer", what);
-    return false;
+bool snn_check_vector(snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v, std::vector<uint32_t> *oc,
+                      std::vector<float> *ov, VecCheck &vc, const char *what, bool report, uint32_t *nz) {
+#define SNN_CHECK_FAIL(...)                           \
+  do {                                                \
+    if (report) ix->fail(SNN_E_INVALID, __VA_ARGS__); \
+    return false;                                     \
+  } while (0)
+  if (nnz && (!c || !v)) SNN_CHECK_FAIL("%s: null coordinate or value pointer", what);
+  const uint32_t dim = ix->cfg.dim;
+  const bool upper_only = (ix->cfg.flags & SNN_UPPER_ONLY) != 0;
+  if (vc.stamps && vc.stamp.size() != dim) {
+    vc.stamp.assign(dim, 0u);
+    vc.tag = 0;
   }
-  scratch.clear();
+  if (vc.stamps && ++vc.tag == 0) {
+    std::fill(vc.stamp.begin(), vc.stamp.end(), 0u);
+    vc.tag = 1;
+  }
+  if (!vc.stamps) vc.scratch.clear();
+  uint32_t nonzero = 0;
   for (uint32_t t = 0; t < nnz; ++t) {
-    if (c[t] >= ix->cfg.dim) {
-      ix->fail(SNN_E_INVALID, "%s: coordinate %u >= dim %u", what, c[t], ix->cfg.dim);
-      return false;
+    if (c[t] >= dim) SNN_CHECK_FAIL("%s: coordinate %u >= dim %u", what, c[t], dim);
+    if (!std::isfinite(v[t])) SNN_CHECK_FAIL("%s: non-finite value at coordinate %u", what, c[t]);
+    if (upper_only && v[t] < 0.0f)
+      SNN_CHECK_FAIL("%s: negative value at coordinate %u (the index keeps no lower bounds)", what, c[t]);
+    if (vc.stamps) {
+      if (vc.stamp[c[t]] == vc.tag) SNN_CHECK_FAIL("%s: duplicate coordinate %u", what, c[t]);
+      vc.stamp[c[t]] = vc.tag;
+    } else {
+      vc.scratch.push_back(c[t]);
     }
-    if (!std::isfinite(v[t])) {
-      ix->fail(SNN_E_INVALID, "%s: non-finite value at coordinate %u", what, c[t]);
-      return false;
-    }
-    if ((ix->cfg.flags & SNN_UPPER_ONLY) && v[t] < 0.0f) {
-      ix->fail(SNN_E_INVALID, "%s: negative value at coordinate %u (the index keeps no lower bounds)", what, c[t]);
-      return false;
-    }
-    scratch.push_back(c[t]);
+    nonzero += v[t] != 0.0f;
   }
-  std::sort(scratch.begin(), scratch.end());
-  for (size_t t = 1; t < scratch.size(); ++t)
-    if (scratch[t] == scratch[t - 1]) {
-      ix->fail(SNN_E_INVALID, "%s: duplicate coordinate %u", what, scratch[t]);
-      return false;
-    }
-  for (uint32_t t = 0; t < nnz; ++t)
-    if (v[t] != 0.0f) {
-      oc.push_back(c[t]);
-      ov.push_back(v[t]);
-    }
+  if (!vc.stamps) {
+    std::sort(vc.scratch.begin(), vc.scratch.end());
+    for (size_t t = 1; t < vc.scratch.size(); ++t)
+      if (vc.scratch[t] == vc.scratch[t - 1]) SNN_CHECK_FAIL("%s: duplicate coordinate %u", what, vc.scratch[t]);
+  }
+#undef SNN_CHECK_FAIL
+  if (oc && ov)
+    for (uint32_t t = 0; t < nnz; ++t)
+      if (v[t] != 0.0f) {
+        oc->push_back(c[t]);
+        ov->push_back(v[t]);
+      }
+  if (nz) *nz = nonzero;
   return true;
+}
+
+// Runs f(begin, end) over [0, n) split into contiguous ranges, one per host
+// thread (at most 16, at least min_per items each); small n runs inline.
+template <class F>
+static void par_ranges(uint64_t n, uint64_t min_per, F &&f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  unsigned T = (unsigned)std::min<uint64_t>(std::min(hw, 16u), n / min_per);
+  if (T <= 1) {
+    f((uint64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (unsigned t = 1; t < T; ++t) th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+  f((uint64_t)0, n / T);
+  for (std::thread &x : th) x.join();
+}
+
+// memcpy split over host threads (pinned staging of large uploads)
+static void par_memcpy(void *dst, const void *src, size_t bytes) {
+  const size_t kPiece = (size_t)1 << 20;
+  par_ranges((bytes + kPiece - 1) / kPiece, 4, [&](uint64_t a, uint64_t b) {
+    const size_t lo = (size_t)a * kPiece, hi = std::min(bytes, (size_t)b * kPiece);
+    if (hi > lo) memcpy((char *)dst + lo, (const char *)src + lo, hi - lo);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -327,18 +368,20 @@ snn_status snn_index::upload_and_insert(const std::vector<uint32_t> &slots, cons
   memcpy(hp + o_ids, ids.data() + r0, n * 4);
   uint64_t *ip = (uint64_t *)(hp + o_ptr);
   for (size_t r = 0; r <= n; ++r) ip[r] = indptr[r0 + r] - e0;
-  memcpy(hp + o_c, coords.data() + e0, ne * 4);
-  memcpy(hp + o_v, vals.data() + e0, ne * 4);
+  par_memcpy(hp + o_c, coords.data() + e0, ne * 4);
+  par_memcpy(hp + o_v, vals.data() + e0, ne * 4);
   const size_t o_off = (o_v + ne * 4 + 7) / 8 * 8;
   if (has_fwd) memcpy(hp + o_off, doc_off.data(), n * 8);
   char *dp = (char *)up.p;
   HIP_TRY(this, hipMemcpyAsync(dp, hp, has_fwd ? o_off + n * 8 : o_v + ne * 4, hipMemcpyHostToDevice, stream),
           "insert copy");
+  HIP_TRY(this, prof_update(0, (uint32_t)n, false), "event");
   HIP_TRY(this,
           launch_insert(dev, (uint32_t)n, (uint32_t *)(dp + o_slots), (uint32_t *)(dp + o_ids),
                         (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), (float *)(dp + o_v), fw,
                         has_fwd ? (uint64_t *)(dp + o_off) : nullptr, stream),
           "insert kernel");
+  HIP_TRY(this, prof_update(0, (uint32_t)n, true), "event");
   HIP_TRY(this, hipStreamSynchronize(stream), "insert sync");
   return SNN_OK;
 }
@@ -348,25 +391,74 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
   if (!ix) return SNN_E_INVALID;
   if (n == 0) return SNN_OK;
   if (!ids || !indptr) return ix->fail(SNN_E_INVALID, "insert: null ids or indptr");
-  // validate everything first (all-or-nothing)
-  std::vector<uint32_t> oc, scratch, slot_of(n);
-  std::vector<float> ov;
-  std::vector<uint64_t> optr(n + 1, 0);
-  std::unordered_map<uint32_t, uint32_t> seen;
-  for (uint32_t r = 0; r < n; ++r) {
-    if (ids[r] == 0xFFFFFFFFu) return ix->fail(SNN_E_INVALID, "insert: id 0xFFFFFFFF is reserved");
-    if (ix->id2slot.count(ids[r])) return ix->fail(SNN_E_EXISTS, "insert: id %u is already live", ids[r]);
-    if (!seen.emplace(ids[r], r).second) return ix->fail(SNN_E_INVALID, "insert: id %u twice in one batch", ids[r]);
-    if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "insert: indptr not monotone");
-    uint64_t len = indptr[r + 1] - indptr[r];
-    if (len > ix->cfg.dim) return ix->fail(SNN_E_INVALID, "insert: vector with more entries than dim");
-    if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "insert"))
-      return SNN_E_INVALID;
-    optr[r + 1] = oc.size();
+  // Validate everything first (all-or-nothing). The error reported is the one
+  // of the first bad row, with a row's id checked before its vector: the ids
+  // in order on this thread, the vectors on several.
+  uint32_t r_id = n;
+  snn_status id_st = SNN_OK;
+  {
+    std::unordered_map<uint32_t, uint32_t> seen;
+    seen.reserve((size_t)n * 2);
+    for (uint32_t r = 0; r < n && r_id == n; ++r) {
+      if (ids[r] == 0xFFFFFFFFu)
+        id_st = ix->fail(SNN_E_INVALID, "insert: id 0xFFFFFFFF is reserved");
+      else if (ix->id2slot.count(ids[r]))
+        id_st = ix->fail(SNN_E_EXISTS, "insert: id %u is already live", ids[r]);
+      else if (!seen.emplace(ids[r], r).second)
+        id_st = ix->fail(SNN_E_INVALID, "insert: id %u twice in one batch", ids[r]);
+      if (id_st != SNN_OK) r_id = r;
+    }
   }
+  const uint64_t dim = ix->cfg.dim;
+  std::vector<uint64_t> optr((size_t)n + 1, 0);  // non-zeros per row, then their offsets
+  std::atomic<uint32_t> r_vec{r_id};             // first row with a bad vector
+  par_ranges(r_id, 1024, [&](uint64_t a, uint64_t b) {
+    VecCheck vc;
+    vc.stamps = b - a >= 256 && dim <= ((uint64_t)1 << 20);
+    for (uint64_t r = a; r < b; ++r) {
+      if (r >= r_vec.load(std::memory_order_relaxed)) return;  // an earlier row failed
+      uint32_t nz = 0;
+      const bool ok = indptr[r + 1] >= indptr[r] && indptr[r + 1] - indptr[r] <= dim &&
+                      snn_check_vector(ix, (uint32_t)(indptr[r + 1] - indptr[r]), coords + indptr[r],
+                                       vals + indptr[r], nullptr, nullptr, vc, "insert", false, &nz);
+      if (!ok) {
+        uint32_t cur = r_vec.load(std::memory_order_relaxed);
+        while ((uint32_t)r < cur && !r_vec.compare_exchange_weak(cur, (uint32_t)r)) {
+        }
+        return;
+      }
+      optr[r + 1] = nz;
+    }
+  });
+  const uint32_t r_bad = r_vec.load();
+  if (r_bad < r_id) {  // the first bad row has a good id: say what is wrong with its vector
+    if (indptr[r_bad + 1] < indptr[r_bad]) return ix->fail(SNN_E_INVALID, "insert: indptr not monotone");
+    const uint64_t len = indptr[r_bad + 1] - indptr[r_bad];
+    if (len > dim) return ix->fail(SNN_E_INVALID, "insert: vector with more entries than dim");
+    VecCheck vc;
+    snn_check_vector(ix, (uint32_t)len, coords + indptr[r_bad], vals + indptr[r_bad], nullptr, nullptr, vc, "insert");
+    return SNN_E_INVALID;
+  }
+  if (r_id < n) return id_st;
   size_t avail = ix->free_slots.size() + (ix->cap - ix->next_fresh);
   if (n > avail) return ix->fail(SNN_E_FULL, "insert: %u vectors but only %zu free slots", n, avail);
+  // the non-zero entries, packed
+  for (uint32_t r = 0; r < n; ++r) optr[r + 1] += optr[r];
+  std::vector<uint32_t> oc(optr[n]);
+  std::vector<float> ov(optr[n]);
+  par_ranges(n, 1024, [&](uint64_t a, uint64_t b) {
+    for (uint64_t r = a; r < b; ++r) {
+      uint64_t o = optr[r];
+      for (uint64_t e = indptr[r]; e < indptr[r + 1]; ++e)
+        if (vals[e] != 0.0f) {
+          oc[o] = coords[e];
+          ov[o] = vals[e];
+          ++o;
+        }
+    }
+  });
   // assign slots: reuse freed columns first (Section 4.3), then fresh ones
+  std::vector<uint32_t> slot_of(n);
   std::vector<uint32_t> vid(ids, ids + n);
   for (uint32_t r = 0; r < n; ++r) {
     if (!ix->free_slots.empty()) {
@@ -386,12 +478,15 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
     if (st != SNN_OK) return st;  // device error: the index is no longer consistent
     r0 = r1;
   }
+  ix->id2slot.reserve(ix->id2slot.size() + n);
   for (uint32_t r = 0; r < n; ++r) {
     const uint32_t s = slot_of[r];
     ix->id2slot[ids[r]] = s;
     ix->slot_id[s] = ids[r];
-    ix->fwd[s].assign(oc.begin() + optr[r], oc.begin() + optr[r + 1]);
   }
+  par_ranges(n, 1024, [&](uint64_t a, uint64_t b) {  // distinct slots: distinct vectors
+    for (uint64_t r = a; r < b; ++r) ix->fwd[slot_of[r]].assign(oc.begin() + optr[r], oc.begin() + optr[r + 1]);
+  });
   ix->live += n;
   ix->mutations++;
   return SNN_OK;
@@ -449,10 +544,12 @@ snn_status snn_index::upload_and_delete(const std::vector<uint32_t> &slots, cons
   if (ne) memcpy(hp + o_c, co.data(), ne * 4);
   char *dp = (char *)up.p;
   HIP_TRY(this, hipMemcpyAsync(dp, hp, o_c + ne * 4, hipMemcpyHostToDevice, stream), "delete copy");
+  HIP_TRY(this, prof_update(1, (uint32_t)n, false), "event");
   HIP_TRY(this,
           launch_delete(dev, (uint32_t)n, (uint32_t *)dp, (uint64_t *)(dp + o_ptr), (uint32_t *)(dp + o_c), clear_bits,
                         clear_live, stream),
           "delete kernel");
+  HIP_TRY(this, prof_update(1, (uint32_t)n, true), "event");
   HIP_TRY(this, hipStreamSynchronize(stream), "delete sync");
   return SNN_OK;
 }
@@ -939,17 +1036,14 @@ static snn_status search_host(snn_index *ix, uint32_t nq, const uint64_t *indptr
   if (st != SNN_OK) return st;
   if (nq == 0) return SNN_OK;
   if (!indptr || !out_ids || !out_scores || !out_counts) return ix->fail(SNN_E_INVALID, "search: null pointer");
-  std::vector<uint32_t> oc, scratch;
-  std::vector<float> ov;
+  VecCheck vc;
   uint64_t max_len = 0;
   for (uint32_t r = 0; r < nq; ++r) {
     if (indptr[r + 1] < indptr[r]) return ix->fail(SNN_E_INVALID, "search: indptr not monotone");
     uint64_t len = indptr[r + 1] - indptr[r];
     if (len > (uint64_t)kPrepCap) return ix->fail(SNN_E_INVALID, "search: a query has more than %d entries", kPrepCap);
     max_len = std::max(max_len, len);
-    oc.clear();
-    ov.clear();
-    if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], oc, ov, scratch, "search"))
+    if (!snn_check_vector(ix, (uint32_t)len, coords + indptr[r], vals + indptr[r], nullptr, nullptr, vc, "search"))
       return SNN_E_INVALID;
   }
   const uint64_t total = indptr[nq];
@@ -1133,6 +1227,47 @@ hipEvent_t snn_index::prof_event() {
   hipEvent_t e = nullptr;
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
+}
+
+// While profiling, one event on the index's stream before (end = false) or
+// after (end = true) an update kernel.
+hipError_t snn_index::prof_update(int which, uint32_t docs, bool end) {
+  if (!prof_on) return hipSuccess;
+  hipEvent_t e = prof_event();
+  if (!e) return hipErrorOutOfMemory;
+  hipError_t r = hipEventRecord(e, stream);
+  if (r != hipSuccess) {
+    prof_pool.push_back(e);
+    return r;
+  }
+  prof_upd[which].push_back(e);
+  if (end) prof_upd_docs[which].push_back(docs);
+  return hipSuccess;
+}
+
+extern "C" snn_status snn_profile_read_updates(snn_index *ix, double *insert_ms, uint64_t *insert_docs,
+                                               double *delete_ms, uint64_t *delete_docs) {
+  if (!ix) return SNN_E_INVALID;
+  double ms_out[2] = {0, 0};
+  uint64_t docs_out[2] = {0, 0};
+  for (int w = 0; w < 2; ++w) {
+    std::vector<hipEvent_t> &ev = ix->prof_upd[w];
+    for (size_t i = 0; i + 1 < ev.size(); i += 2) {
+      HIP_TRY(ix, hipEventSynchronize(ev[i + 1]), "event sync");
+      float ms = 0;
+      HIP_TRY(ix, hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "event time");
+      ms_out[w] += ms;
+    }
+    for (uint32_t d : ix->prof_upd_docs[w]) docs_out[w] += d;
+    for (hipEvent_t e : ev) ix->prof_pool.push_back(e);
+    ev.clear();
+    ix->prof_upd_docs[w].clear();
+  }
+  if (insert_ms) *insert_ms = ms_out[0];
+  if (insert_docs) *insert_docs = docs_out[0];
+  if (delete_ms) *delete_ms = ms_out[1];
+  if (delete_docs) *delete_docs = docs_out[1];
+  return SNN_OK;
 }
 
 extern "C" snn_status snn_profile_enable(snn_index *ix, int on) {

@@ -197,9 +197,23 @@ struct GraphCache {
 }  // namespace snn
 
 void snn_filter_release(struct snn_index *ix);
+// Working state of the duplicate-coordinate check: a sort of the coordinates,
+// or, over many vectors of a moderate dimension, one stamp per coordinate (the
+// tag of the last vector that held it), so each vector costs O(nnz).
+struct VecCheck {
+  std::vector<uint32_t> scratch;
+  std::vector<uint32_t> stamp;
+  uint32_t tag = 0;
+  bool stamps = false;
+};
+// Validates one vector (coordinates < dim, finite values, no duplicate
+// coordinates, no negative values without an L half). On success appends its
+// non-zero entries to *oc / *ov when given and stores their count in *nz when
+// given. On failure records the reason with ix->fail when `report` (only then
+// is ix written, so unreported checks may run on several threads).
 bool snn_check_vector(struct snn_index *ix, uint32_t nnz, const uint32_t *c, const float *v,
-                      std::vector<uint32_t> &oc, std::vector<float> &ov, std::vector<uint32_t> &scratch,
-                      const char *what);
+                      std::vector<uint32_t> *oc, std::vector<float> *ov, VecCheck &vc, const char *what,
+                      bool report = true, uint32_t *nz = nullptr);
 
 struct snn_index {
   snn_config cfg{};
@@ -253,7 +267,12 @@ struct snn_index {
   uint32_t prof_accum_n = 0;
   std::vector<hipEvent_t> prof_events;  // pairs (start, end) recorded since the last read
   std::vector<hipEvent_t> prof_pool;
+  // (start, end) pairs around the insert and the delete kernels, and the
+  // documents each pair covered, recorded since the last read
+  std::vector<hipEvent_t> prof_upd[2];
+  std::vector<uint32_t> prof_upd_docs[2];
   hipEvent_t prof_event();
+  hipError_t prof_update(int which, uint32_t docs, bool end);
 
   snn_status fail(snn_status st, const char *fmt, ...);
   snn_status hip_fail(hipError_t e, const char *what);

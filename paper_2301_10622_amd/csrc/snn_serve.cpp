@@ -88,8 +88,8 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
     std::unordered_set<uint32_t> live;
     live.reserve(ix->id2slot.size() * 2 + n);
     for (auto &kv : ix->id2slot) live.insert(kv.first);
-    std::vector<uint32_t> oc, scratch;
-    std::vector<float> ov;
+    VecCheck vc;
+    vc.stamps = tr->n >= 256 && ix->cfg.dim <= (1u << 20);
     size_t cap_left = ix->free_slots.size() + (ix->cap - ix->next_fresh);
     for (uint32_t r = 0; r < n; ++r) {
       if (r && tr->arrival_s[r] < tr->arrival_s[r - 1]) return ix->fail(SNN_E_INVALID, "serve: arrivals not sorted");
@@ -99,10 +99,8 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
       if (kd == 0 || kd == 1) {
         if (len > (kd == 0 ? (uint64_t)kPrepCap : (uint64_t)ix->cfg.dim))
           return ix->fail(SNN_E_INVALID, "serve: request %u has too many entries", r);
-        oc.clear();
-        ov.clear();
-        if (!snn_check_vector(ix, (uint32_t)len, tr->coords + tr->indptr[r], tr->vals + tr->indptr[r], oc, ov,
-                              scratch, "serve"))
+        if (!snn_check_vector(ix, (uint32_t)len, tr->coords + tr->indptr[r], tr->vals + tr->indptr[r], nullptr,
+                              nullptr, vc, "serve"))
           return SNN_E_INVALID;
       }
       if (kd == 0) {

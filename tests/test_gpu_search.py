@@ -233,6 +233,83 @@ def test_streaming_history_equals_fresh_index():
         assert np.array_equal(u.astype(np.float64), ou) and np.array_equal(l.astype(np.float64), ol)
 
 
+def test_update_batches_of_ragged_sizes():
+    """Insert and delete batches of sizes below and between multiples of 8 (the
+    update kernels split a batch into 8 runs, one per XCD): every live sketch
+    column is the oracle's, bit for bit, and searches match the oracle."""
+    P = _lib()
+    pool = gen.sparse_rows(41, 6000, 1000, 1.1, np.random.default_rng(41).integers(20, 61, 6000), "normal")
+    qs = gen.sparse_rows(42, 16, 1000, 1.1, np.full(16, 20), "normal")
+    ix = _fresh(1000, 32, 1, 8000, seed=6)
+    live = {}
+    nxt = 0
+    for size in (1, 3, 7, 9, 13, 1001, 4097):
+        rows = np.arange(nxt, nxt + size)
+        sub = pool.take(rows)
+        ids = (rows * 5 + 2).astype(np.uint32)
+        ix.insert_batch(ids, sub.indptr, sub.coords, sub.vals)
+        live.update({int(i): int(r) for i, r in zip(ids, rows)})
+        nxt += size
+    rng = np.random.default_rng(43)
+    for size in (1, 5, 11, 333):
+        dels = rng.choice(sorted(live), size, replace=False)
+        ix.delete_batch(dels)
+        for d in dels:
+            del live[int(d)]
+    # refill freed slots with a batch of 349 (not a multiple of 8)
+    rows = np.arange(nxt, nxt + 349)
+    sub = pool.take(rows)
+    ids = (rows * 5 + 2).astype(np.uint32)
+    ix.insert_batch(ids, sub.indptr, sub.coords, sub.vals)
+    live.update({int(i): int(r) for i, r in zip(ids, rows)})
+    assert ix.live_count == len(live)
+    lid = np.array(sorted(live), dtype=np.uint32)
+    for i in lid:
+        c, v = pool.row(live[int(i)])
+        u, l = ix.read_sketch(int(i))
+        ou, ol, _ = O.sketch(c, v, 32, 1, 6)
+        assert np.array_equal(u.astype(np.float64), ou) and np.array_equal(l.astype(np.float64), ol), int(i)
+    ora = O.Index(pool.take([live[int(i)] for i in lid]), 1000, 32, 1, 6, ids=lid)
+    ids, sc, cnt = ix.search_batch(qs.indptr, qs.coords, qs.vals, 20)
+    parity.check_batch(ids, sc, cnt, ora, qs, 20, what="ragged updates")
+
+
+def test_large_batch_errors_name_the_first_bad_row():
+    """Batches large enough to be validated on several host threads report the
+    error of the first bad row (a row's id before its vector) and insert nothing."""
+    P = _lib()
+    ix = _fresh(1000, 32, 1, 20000, seed=7)
+    pool = gen.sparse_rows(51, 12000, 1000, 1.1, np.full(12000, 30), "normal")
+    ix.insert(5_000_000, [1, 2], [1.0, 2.0])
+
+    def attempt(vec_row, id_row, dup_row=None):
+        ids = np.arange(12000, dtype=np.uint32)
+        c, v = pool.coords.copy(), pool.vals.copy()
+        if vec_row is not None:
+            v[pool.indptr[vec_row] + 3] = np.nan
+        if dup_row is not None:
+            c[pool.indptr[dup_row] + 5] = c[pool.indptr[dup_row] + 9]
+        if id_row is not None:
+            ids[id_row] = 5_000_000
+        with pytest.raises(P.SnnError) as e:
+            ix.insert_batch(ids, pool.indptr, c, v)
+        assert ix.live_count == 1
+        return e.value
+
+    e = attempt(9000, 2000)
+    assert e.status == -2 and "already live" in str(e)
+    e = attempt(1000, 6000)
+    assert e.status == -1 and "non-finite" in str(e)
+    e = attempt(11999, None)
+    assert e.status == -1 and "non-finite" in str(e)
+    e = attempt(None, 11999)
+    assert e.status == -2
+    e = attempt(7000, None, dup_row=4000)
+    assert e.status == -1 and "duplicate coordinate %d" % pool.coords[pool.indptr[4000] + 9] in str(e)
+    ix.insert_batch(np.arange(12000, dtype=np.uint32), pool.indptr, pool.coords, pool.vals)
+    assert ix.live_count == 12001
+
+
 def _dev_batch(q):
     import torch
 
