@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -169,7 +170,13 @@ static void par_ranges(uint64_t n, uint64_t min_per, F &&f) {
   }
   std::vector<std::thread> th;
   th.reserve(T - 1);
-  for (unsigned t = 1; t < T; ++t) th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+  for (unsigned t = 1; t < T; ++t) {
+    try {
+      th.emplace_back([&f, n, t, T] { f(n * t / T, n * (t + 1) / T); });
+    } catch (const std::system_error &) {  // no thread to be had: run the range here
+      f(n * t / T, n * (t + 1) / T);
+    }
+  }
   f((uint64_t)0, n / T);
   for (std::thread &x : th) x.join();
 }
