@@ -634,6 +634,7 @@ __device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &s
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
+  if (nq == 0) return;  // an empty query list: no queue traffic at all
   for (uint32_t step = 0; step < X; ++step) {
     const uint32_t x = (home + step) % X;
     const uint32_t tiles_x = a.tiles > x ? (a.tiles - x + X - 1) / X : 0u;
@@ -690,6 +691,7 @@ void k_tiles_persistent_grouped(TileArgs a) {
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
+  if (nq == 0) return;  // an empty query list: no queue traffic at all
   const uint32_t ng = (nq + Q - 1) / Q;
   for (uint32_t step = 0; step < X; ++step) {
     const uint32_t x = (home + step) % X;
