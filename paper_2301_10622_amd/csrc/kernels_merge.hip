@@ -33,10 +33,35 @@ constexpr int kSelWaves = kSelBlock / 64;
 constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
 
+// Inclusive prefix sum of v over the workgroup's threads, and the total: a
+// shuffle scan inside each wave, then the 8 wave totals through LDS (two
+// barriers, where a scan over the threads in LDS takes two per doubling).
+__device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  uint32_t off = 0, t = 0;
+#pragma unroll
+  for (int w = 0; w < kSelWaves; ++w) {
+    const uint32_t sw = wsum[w];
+    off += w < wave ? sw : 0u;
+    t += sw;
+  }
+  __syncthreads();  // wsum is free for the next scan
+  total = t;
+  return x + off;
+}
+
 template <bool kPay, bool kSorted>
 __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   __shared__ uint32_t hist[kSelBins];
-  __shared__ uint32_t part[kSelBlock];
+  __shared__ uint32_t wsum[kSelWaves];
   __shared__ uint64_t sel[kSorted ? kMaxK : 1];
   __shared__ uint32_t sels[kPay && kSorted ? kMaxK : 1];
   __shared__ uint32_t sh_bin, sh_need, sh_pos;
@@ -63,17 +88,10 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   } else {
     for (uint32_t g = (uint32_t)tid; g < G; g += kSelBlock) mine += cnts[g];
   }
-  part[tid] = mine;
-  __syncthreads();
-  for (int off = 1; off < kSelBlock; off <<= 1) {  // inclusive scan
-    const uint32_t v = tid >= off ? part[tid - off] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  const uint32_t M = part[kSelBlock - 1];
+  uint32_t M;
+  const uint32_t incl = sel_scan(mine, wsum, M);
   if (scan) {
-    uint32_t o = part[tid] - mine;
+    uint32_t o = incl - mine;
     for (uint32_t g = (uint32_t)tid * gper; g < min(G, ((uint32_t)tid + 1) * gper); ++g) {
       goff[g] = o;
       o += cnts[g];
@@ -153,15 +171,9 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       const uint32_t b0 = (uint32_t)tid * per;
       uint32_t s = 0;
       for (uint32_t b = b0; b < b0 + per && b < nb; ++b) s += hist[b];
-      part[tid] = s;
-      __syncthreads();
-      for (int off = 1; off < kSelBlock; off <<= 1) {
-        const uint32_t v = tid + off < kSelBlock ? part[tid + off] : 0u;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-      }
-      uint32_t above = part[tid] - s;
+      uint32_t tot;
+      const uint32_t pre = sel_scan(s, wsum, tot);
+      uint32_t above = tot - pre;  // keys in the bins of the threads after this one
       for (int b = (int)min(b0 + per, nb) - 1; b >= (int)b0; --b) {
         const uint32_t h = hist[b];
         if (above < need && above + h >= need) {
