@@ -32,6 +32,7 @@ constexpr int kSelBlock = 512;
 constexpr int kSelWaves = kSelBlock / 64;
 constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
+constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 per query)
 
 // Inclusive prefix sum of v over the workgroup's threads, and the total: a
 // shuffle scan inside each wave, then the 8 wave totals through LDS (two
@@ -104,8 +105,36 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   // binary search in goff, so no lane idles on a short group; otherwise wave w
   // walks groups w, w + 8, ..., its lanes the group's keys.
   const bool flat = scan && M < 64u * G;
+  // At most kSelCache keys per thread: read them (and their groups) once into
+  // registers and serve every pass from there.
+  const bool cached = flat && M <= (uint32_t)(kSelCache * kSelBlock);
+  uint64_t ck[kSelCache];
+  uint32_t cg[kSelCache], ce[kSelCache];
+  if (cached) {
+#pragma unroll
+    for (int u = 0; u < kSelCache; ++u) {
+      const uint32_t i = (uint32_t)tid + (uint32_t)u * kSelBlock;
+      ck[u] = 0;
+      cg[u] = ce[u] = 0;
+      if (i < M) {
+        uint32_t lo = 0, hi = G;  // goff[lo] <= i < goff[hi]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (goff[mid] <= i) lo = mid;
+          else hi = mid;
+        }
+        cg[u] = lo;
+        ce[u] = i - goff[lo];
+        ck[u] = base[(size_t)lo * a.in_stride + ce[u]];
+      }
+    }
+  }
   auto for_each = [&](auto f) {
-    if (flat) {
+    if (cached) {
+#pragma unroll
+      for (int u = 0; u < kSelCache; ++u)
+        if ((uint32_t)tid + (uint32_t)u * kSelBlock < M) f(ck[u], cg[u], ce[u]);
+    } else if (flat) {
       constexpr int U = 4;  // keys in flight per thread
       for (uint32_t i0 = (uint32_t)tid; i0 < M; i0 += U * kSelBlock) {
         uint64_t kk[U];
