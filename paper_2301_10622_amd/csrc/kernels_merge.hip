@@ -33,6 +33,7 @@ constexpr int kSelWaves = kSelBlock / 64;
 constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
 constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 per query)
+constexpr int kSelU = 4;                 // keys of a group per lane in flight (large groups)
 
 // Inclusive prefix sum of v over the workgroup's threads, and the total: a
 // shuffle scan inside each wave, then the 8 wave totals through LDS (two
@@ -161,18 +162,28 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
           if (i0 + (uint32_t)u * kSelBlock < M) f(kk[u], gg[u], ee[u]);
       }
     } else {
-      // two groups at a time, so two groups' keys are in flight per lane
+      // two groups at a time and kSelU keys of each per lane, so 2 kSelU
+      // loads are in flight per lane
       for (uint32_t g = (uint32_t)wave; g < G; g += 2 * kSelWaves) {
         const uint32_t g2 = g + kSelWaves;
         const uint32_t c1 = scan ? goff[g + 1] - goff[g] : cnts[g];
         const uint32_t c2 = g2 < G ? (scan ? goff[g2 + 1] - goff[g2] : cnts[g2]) : 0u;
         const uint64_t *s1 = base + (size_t)g * a.in_stride;
         const uint64_t *s2 = base + (size_t)g2 * a.in_stride;
-        for (uint32_t e = (uint32_t)lane; e < max(c1, c2); e += 64) {
-          const uint64_t k1 = e < c1 ? s1[e] : 0ull;
-          const uint64_t k2 = e < c2 ? s2[e] : 0ull;
-          if (e < c1) f(k1, g, e);
-          if (e < c2) f(k2, g2, e);
+        for (uint32_t e0 = (uint32_t)lane; e0 < max(c1, c2); e0 += 64u * kSelU) {
+          uint64_t k1[kSelU], k2[kSelU];
+#pragma unroll
+          for (int u = 0; u < kSelU; ++u) {
+            const uint32_t e = e0 + 64u * (uint32_t)u;
+            k1[u] = e < c1 ? s1[e] : 0ull;
+            k2[u] = e < c2 ? s2[e] : 0ull;
+          }
+#pragma unroll
+          for (int u = 0; u < kSelU; ++u) {
+            const uint32_t e = e0 + 64u * (uint32_t)u;
+            if (e < c1) f(k1[u], g, e);
+            if (e < c2) f(k2[u], g2, e);
+          }
         }
       }
     }
