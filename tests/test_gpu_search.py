@@ -310,6 +310,33 @@ def test_large_batch_errors_name_the_first_bad_row():
     assert ix.live_count == 12001
 
 
+@pytest.mark.parametrize("k", [51, 60])
+def test_select_around_the_register_cache(k):
+    """80 tiles of 4,096 slots: the plain form's per-query select sees at most
+    80 k keys, so at k = 51 (at most 4,080) every key is held in registers and
+    at k = 60 (up to 4,800, still fewer than 64 per tile on average) most
+    queries exceed the 4,096 the registers hold and take the path that reads
+    the keys again; both give the batched form's bits and the oracle's top-k."""
+    P = _lib()
+    docs = gen.small_docs(61, 80 * 4096)
+    qs = gen.small_queries(62, 8)
+    ix = _fresh(1000, 32, 1, docs.rows, seed=8)
+    P.load_docs(ix, docs)
+    ix.set_schedule(16, 16, 2048, True, 1)
+    import torch
+
+    tens = _dev_batch(qs)
+    plain = _dev_search(ix, tens, k, 0)
+    work = ix.last_batch_work()
+    batched = _dev_search(ix, tens, k, 1)
+    for x, y in zip(plain, batched):
+        assert np.array_equal(x, y)
+    per_query = work["candidates"] / qs.rows
+    assert (per_query <= 4096) if k == 51 else (per_query > 4096)
+    ora = O.Index(docs, 1000, 32, 1, 8)
+    parity.check_batch(plain[0].astype(np.uint32), plain[1], plain[2], ora, qs, k, what="select cache k=%d" % k)
+
+
 def _dev_batch(q):
     import torch
 
