@@ -299,6 +299,11 @@ def main():
         t = time.perf_counter()
         eids, esc, _, ecnt = ora.search(sample, args.k, exact=True, threads=threads)
         t_exact = time.perf_counter() - t
+        # the same estimate on one thread, over the first 16 queries of the sample
+        S1 = min(16, S)
+        t = time.perf_counter()
+        ora.search(w.queries.take(range(S1)), args.k, threads=1)
+        t_one = time.perf_counter() - t
         gids = outs[(best, args.k)][0][:S].cpu().numpy().astype(np.int64)
         gcnt = outs[(best, args.k)][2][:S].cpu().numpy()
         rec = []
@@ -332,9 +337,11 @@ def main():
                                   "kind": "oracle",
                                   "sample": "first %d of the %d queries, k=%d, FP64 coordinate-at-a-time estimate "
                                             "+ FindLargest; index build %.1fs excluded" % (S, nq, args.k, t_build),
-                                  "exact_brute_force_qps": round(S / t_exact, 2)}
-        log("oracle: %.2f q/s (estimate), %.2f q/s (exact); recall@%d %.4f" % (
-            S / t_est, S / t_exact, args.k, result["recall_at_%d" % args.k]))
+                                  "exact_brute_force_qps": round(S / t_exact, 2),
+                                  "single_thread_qps": round(S1 / t_one, 2),
+                                  "host": host_cpu()}
+        log("oracle: %.2f q/s (estimate), %.2f q/s (exact), %.2f q/s on one thread; recall@%d %.4f" % (
+            S / t_est, S / t_exact, S1 / t_one, args.k, result["recall_at_%d" % args.k]))
     if variants_res:
         result["sketch_variants"] = {v: {f: ({kk: (round(x, 4) if isinstance(x, float) else x) for kk, x in d.items()}
                                              if isinstance(d, dict) else d) for f, d in r.items()}
@@ -364,29 +371,50 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count (as lscpu and nproc give them)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+
+
 def update_kernels(P, np, ix, w, build, n_upd):
     """Docs/s and algorithmic GB/s of the insert and delete kernels.
 
     Algorithmic bytes per document (Alg. 5 / Section 4.3): insert reads its
-    psi_d (coordinate, value) pairs (8 B each), writes the 2m-entry sketch
-    column (4 B each), appends the slot to psi_d lists (4 B each) and, with the
-    forward store, copies the pairs there (8 B each); delete reads the psi_d
-    stored coordinates (4 B each) and removes the slot from psi_d lists (4 B
-    each)."""
+    psi_d (coordinate, value) pairs (8 B each) and writes the 2m-entry sketch
+    column (4 B each), 8 psi_d + 8m; counted in full it also appends the slot
+    to psi_d lists (4 B each) and, with the forward store, copies the pairs
+    there (8 B each), 20 psi_d + 8m. Delete reads the psi_d stored coordinates
+    (4 B each) and removes the slot from psi_d lists (4 B each), 8 psi_d; the
+    column stays as it is."""
     nnz = np.diff(w.docs.indptr)
     two_m = 2 * w.m
     res = {}
 
-    def line(tag, ms, docs, nbytes):
+    def line(tag, ms, docs, nbytes, full=None):
         r = {"docs": int(docs), "kernel_ms": round(ms, 3), "docs_per_s": round(docs / (ms / 1000.0), 1),
              "alg_GBps": round(nbytes / (ms / 1000.0) / 1e9, 1),
              "hbm_frac": round(nbytes / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)}
-        log("%-14s %8d docs  %8.3f ms  %12.0f docs/s  alg %7.1f GB/s (%.1f%% of HBM peak)" % (
-            tag, docs, ms, r["docs_per_s"], r["alg_GBps"], 100 * r["hbm_frac"]))
+        if full is not None:
+            r["alg_GBps_full"] = round(full / (ms / 1000.0) / 1e9, 1)
+        log("%-14s %8d docs  %8.3f ms  %12.0f docs/s  alg %7.1f GB/s (%.1f%% of HBM peak)%s" % (
+            tag, docs, ms, r["docs_per_s"], r["alg_GBps"], 100 * r["hbm_frac"],
+            "" if full is None else "; %.1f GB/s counted in full" % r["alg_GBps_full"]))
         return r
 
-    ins_bytes = lambda psi: float(np.sum(8 * psi + 4 * two_m + 4 * psi + 8 * psi))
-    res["insert_build"] = line("insert build", build["insert_ms"], build["insert_docs"], ins_bytes(nnz))
+    ins_bytes = lambda psi: float(np.sum(8 * psi + 4 * two_m))
+    ins_full = lambda psi: float(np.sum(8 * psi + 4 * two_m + 4 * psi + 8 * psi))
+    res["insert_build"] = line("insert build", build["insert_ms"], build["insert_docs"], ins_bytes(nnz),
+                               ins_full(nnz))
     if n_upd > 0:
         n_upd = min(n_upd, w.docs.rows)
         ids = np.arange(n_upd, dtype=np.uint32)
@@ -398,8 +426,9 @@ def update_kernels(P, np, ix, w, build, n_upd):
         ix.profile(False)
         psi = nnz[:n_upd]
         res["delete"] = line("delete", u["delete_ms"], u["delete_docs"], float(np.sum(8 * psi)))
-        res["insert_reuse"] = line("insert reuse", u["insert_ms"], u["insert_docs"], ins_bytes(psi))
-    res["bytes_per_doc"] = "insert 20 psi_d + 8m (forward store on), delete 8 psi_d"
+        res["insert_reuse"] = line("insert reuse", u["insert_ms"], u["insert_docs"], ins_bytes(psi), ins_full(psi))
+    res["bytes_per_doc"] = ("insert 8 psi_d + 8m (in full, with list appends and the forward store, "
+                            "20 psi_d + 8m); delete 8 psi_d")
     return res
 
 
