@@ -211,6 +211,23 @@ def main():
         log("rerank   k=%d k'=%-5d coords %-4s %8.3f ms/step  %10.0f q/s" % (args.k, kp, c or "all", ms,
                                                                           nq / (ms / 1000.0)))
 
+    # the same batch through the host-buffer call (host validation, upload over
+    # PCIe, the batched search, results back): context, never the headline
+    qh = w.queries
+    host_ids = ix.search_batch(qh.indptr, qh.coords, qh.vals, args.k)[0]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    host_reps = 5
+    for _ in range(host_reps):
+        ix.search_batch(qh.indptr, qh.coords, qh.vals, args.k)
+    host_ms = (time.perf_counter() - t) * 1000.0 / host_reps
+    ref_form = next((n for n in ("batched", "plain", "learned") if (n, args.k) in outs), None)
+    host_api = {"qps": round(nq / (host_ms / 1000.0), 1), "ms_per_batch": round(host_ms, 3),
+                "same_ids_as_device_form": None if ref_form is None else bool(np.array_equal(
+                    host_ids.astype(np.int64), outs[(ref_form, args.k)][0].cpu().numpy().astype(np.int64)))}
+    log("host API  k=%d   %8.3f ms / %d queries  %10.0f q/s (inputs from host memory, results back)" % (
+        args.k, host_ms, nq, host_api["qps"]))
+
     # update kernels (Alg. 5 insert, Section 4.3 delete), timed with HIP events
     # around each launch: the 1M-doc build into fresh slots above, then a delete
     # and re-insert of the first 131,072 documents into the freed slots
@@ -277,6 +294,7 @@ def main():
         "forms": {n: {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()} for n, r in forms.items()},
         "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1),
         "update_kernels": updates,
+        "host_api_search": host_api,
         "schedule": sched,
         "filters": filters,
     }
