@@ -34,6 +34,7 @@ constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
 constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 per query)
 constexpr int kSelU = 4;                 // keys of a group per lane in flight (large groups)
+constexpr uint32_t kSelCmp = 1024;       // keys copied to LDS after the first radix pass
 
 // Inclusive prefix sum of v over the workgroup's threads, and the total: a
 // shuffle scan inside each wave, then the 8 wave totals through LDS (two
@@ -68,6 +69,10 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   __shared__ uint32_t sels[kPay && kSorted ? kMaxK : 1];
   __shared__ uint32_t sh_bin, sh_need, sh_pos;
   __shared__ uint32_t goff[kSelScanMax + 1];  // first key of each group among all the query's keys
+  // after the first radix pass: the keys at or above the bin found, when few
+  __shared__ uint64_t cmp_key[kSelCmp];
+  __shared__ uint32_t cmp_g[kSelCmp], cmp_e[kSelCmp];
+  __shared__ uint32_t cmp_n;
   uint32_t q = a.q0 + blockIdx.y;
   if (a.qlist) {
     if (q >= *as_const(a.nlist)) return;
@@ -130,8 +135,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       }
     }
   }
+  bool compacted = false;
   auto for_each = [&](auto f) {
-    if (cached) {
+    if (compacted) {
+      const uint32_t n = cmp_n;
+      for (uint32_t i = (uint32_t)tid; i < n; i += kSelBlock) f(cmp_key[i], cmp_g[i], cmp_e[i]);
+    } else if (cached) {
 #pragma unroll
       for (int u = 0; u < kSelCache; ++u)
         if ((uint32_t)tid + (uint32_t)u * kSelBlock < M) f(ck[u], cg[u], ce[u]);
@@ -232,6 +241,24 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       if (in_bin == need || pb == 64) {
         T = pb == 64 ? P : (P << (64 - pb));
         break;
+      }
+      // The keys whose first pb bits are at least P (the keep - need above the
+      // bin and the in_bin in it) hold every key still to be decided and every
+      // key to emit. When they are few, one more read copies them to LDS and
+      // the remaining passes and the emission work from there.
+      if (!cached && !compacted && (keep - need) + in_bin <= kSelCmp) {
+        if (tid == 0) cmp_n = 0;
+        __syncthreads();
+        for_each([&](uint64_t key, uint32_t g, uint32_t e) {
+          if ((key >> (64 - pb)) >= P) {
+            const uint32_t pos = atomicAdd(&cmp_n, 1u);
+            cmp_key[pos] = key;
+            cmp_g[pos] = g;
+            cmp_e[pos] = e;
+          }
+        });
+        __syncthreads();
+        compacted = true;
       }
     }
   }
