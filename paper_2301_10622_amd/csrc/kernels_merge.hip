@@ -34,7 +34,10 @@ constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
 constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 per query)
 constexpr int kSelU = 4;                 // keys of a group per lane in flight (large groups)
-constexpr uint32_t kSelCmp = 1024;       // keys copied to LDS after the first radix pass
+// keys copied to LDS after the first radix pass: 1,024, or 4,096 in the form
+// launched for a sorted top-k with k above 512 (more LDS, one workgroup per CU)
+template <bool kBig>
+constexpr uint32_t sel_cmp() { return kBig ? 4096u : 1024u; }
 
 // Inclusive prefix sum of v over the workgroup's threads, and the total: a
 // shuffle scan inside each wave, then the 8 wave totals through LDS (two
@@ -61,8 +64,9 @@ __device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t *wsum, uint32_
   return x + off;
 }
 
-template <bool kPay, bool kSorted>
+template <bool kPay, bool kSorted, bool kBig>
 __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
+  constexpr uint32_t kSelCmp = sel_cmp<kBig>();
   __shared__ uint32_t hist[kSelBins];
   __shared__ uint32_t wsum[kSelWaves];
   __shared__ uint64_t sel[kSorted ? kMaxK : 1];
@@ -331,8 +335,12 @@ hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
   if (sorted ? a.kmax > kMaxK : a.kmax > kMaxKPrime) return hipErrorInvalidValue;
   const bool pay = a.in_slot != nullptr;
   if (pay != (a.res_slots != nullptr)) return hipErrorInvalidValue;
-  if (sorted && !pay) hipLaunchKernelGGL((k_select<false, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else if (!sorted && pay) hipLaunchKernelGGL((k_select<true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  if (sorted && !pay && a.kmax > 512)
+    hipLaunchKernelGGL((k_select<false, true, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else if (sorted && !pay)
+    hipLaunchKernelGGL((k_select<false, true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else if (!sorted && pay)
+    hipLaunchKernelGGL((k_select<true, false, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
   else return hipErrorInvalidValue;  // the two forms the search uses
   return hipGetLastError();
 }
