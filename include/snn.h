@@ -52,7 +52,7 @@ typedef enum {
 
 /* Sketch configuration: Sinnamon_(2m, h) of Alg. 5/6.
  *   dim       n, the dimensionality of the vectors
- *   m         buckets per half of the sketch (U and L each hold m rows)
+ *   m         buckets per half of the sketch (U and L each hold m rows), 1..1024
  *   h         number of random mappings pi_o : [n] -> [m], 1..4
  *   hash_seed the mappings are pi_o(j) = mix64(mix64(hash_seed + o) XOR j) mod m
  *             with mix64 the SplitMix64 output function (Steele, Lea, Flood
@@ -88,8 +88,9 @@ typedef struct snn_index snn_index;
  * default stream) is where the index's own work is enqueued. Device memory for
  * the posting bitmaps (dim x capacity bits), the sketch matrix (2m x capacity
  * float32, the row-major layout of Section 4.1 "Notes on Implementation") and
- * the slot maps is allocated here. Errors: SNN_E_INVALID (dim or m is 0, h not
- * in 1..4, capacity 0 or above 2^31), SNN_E_NOMEM, SNN_E_DEVICE. */
+ * the slot maps is allocated here. Errors: SNN_E_INVALID (dim is 0, m not in
+ * 1..1024, h not in 1..4, capacity 0 or above 2^31), SNN_E_NOMEM,
+ * SNN_E_DEVICE. */
 snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_index **out);
 void snn_destroy(snn_index *ix);
 
@@ -320,6 +321,14 @@ snn_status snn_filter_predict(snn_index *ix, uint32_t nq, const uint64_t *indptr
 snn_status snn_filter_get_params(snn_index *ix, float *params);
 snn_status snn_filter_set_params(snn_index *ix, const float *params, uint64_t feature_seed, uint32_t k);
 snn_status snn_filter_set_delta(snn_index *ix, float delta);
+/* Switch the learned form on (on != 0) or off for the host-buffer calls
+ * snn_search and snn_search_batch, the search(q, k) of the problem statement
+ * (Section 1): while on they run SNN_MODE_LEARNED instead of
+ * SNN_MODE_BATCHED. Results are the same either way; snn_last_batch_status
+ * reports how many queries of the last call fell back to the plain pass.
+ * snn_search_ex / _dev calls keep the mode they are given. Errors:
+ * SNN_E_INVALID (on != 0 without a trained or installed filter). */
+snn_status snn_filter_enable(snn_index *ix, int on);
 /* Loss and gradient of the MLP on B device-resident feature rows X (B x 256)
  * and targets y, with the current compute copies: *loss (host) and grad
  * (device, SNN_MLP_PARAMS floats). Used to check the training kernels. */

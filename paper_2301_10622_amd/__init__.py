@@ -38,7 +38,7 @@ EXPORTS = [
     "snn_read_sketch", "snn_live_count", "snn_last_error", "snn_profile_enable", "snn_profile_read",
     "snn_profile_read_updates", "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
-    "snn_filter_set_params", "snn_filter_set_delta", "snn_mlp_loss_grad", "snn_serve_run",
+    "snn_filter_set_params", "snn_filter_set_delta", "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run",
 ]
 MLP_PARAMS = 49537
 
@@ -155,6 +155,7 @@ def lib():
         L.snn_filter_get_params.argtypes = [P, P]
         L.snn_filter_set_params.argtypes = [P, P, u64, u32]
         L.snn_filter_set_delta.argtypes = [P, ctypes.c_float]
+        L.snn_filter_enable.argtypes = [P, i32]
         L.snn_mlp_loss_grad.argtypes = [P, u32, P, P, P, P]
         L.snn_serve_run.argtypes = [P, P, P, P, P, P, P, P]
         L.snn_live_count.argtypes = [P]
@@ -168,7 +169,7 @@ def lib():
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_profile_read_updates", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
-                     "snn_mlp_loss_grad", "snn_serve_run"):
+                     "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -446,6 +447,10 @@ class Index:
 
     def filter_set_delta(self, delta: float):
         self._check(lib().snn_filter_set_delta(self._h, float(delta)))
+
+    def filter_enable(self, on: bool = True):
+        """search / search_batch (host buffers) run the learned form while on."""
+        self._check(lib().snn_filter_enable(self._h, 1 if on else 0))
 
     def mlp_loss_grad(self, X, y):
         """(loss, grad) of the MLP on device feature rows X and targets y."""

@@ -24,7 +24,6 @@ namespace snn {
 //      copied to its region (doc_off, placed by the host).
 // The caller guarantees the slot's old postings were cleared before (delete).
 // ---------------------------------------------------------------------------
-constexpr int kInsertMaxM = 1024;
 
 // Document of workgroup b in an update launch over n documents (8 * ceil(n / 8)
 // workgroups; those past the last document do nothing).
@@ -112,7 +111,7 @@ hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, 
                          const uint64_t *indptr, const uint32_t *coords, const float *vals, const DevForward &fw,
                          const uint64_t *doc_off, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  if (n > kUpdMaxDocs || ix.m > (uint32_t)kInsertMaxM) return hipErrorInvalidValue;
+  if (n > kUpdMaxDocs || ix.m > kMaxM) return hipErrorInvalidValue;
   if ((doc_off != nullptr) != (fw.ent != nullptr)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_insert, dim3(upd_grid(n)), dim3(64), 2u * ix.m * sizeof(uint32_t), s, ix, n, slots, ids,
                      indptr, coords, vals, fw, doc_off);
@@ -333,6 +332,8 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
   }
   int n = 1;
   while (n < len) n <<= 1;
+  // validation, the non-zero count, and the coordinates of every entry (zero
+  // values included, as in the short path) for the duplicate check
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     uint64_t key = ~0ull;
     if (i < len) {
@@ -342,20 +343,14 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       const uint32_t ab = vb & 0x7FFFFFFFu;
       if (j >= ix.dim || ab >= 0x7F800000u) atomicOr(&bad, 1u);
       if ((ix.flags & kUpperOnly) && ab != 0u && (vb >> 31)) atomicOr(&bad, 1u);  // no L to bound it
-      if (ab != 0u) {
-        atomicAdd(&nz, 1u);
-        key = ((uint64_t)(~ab) << 32) | ((uint64_t)(j & 0x7FFFFFFFu) << 1) | (uint64_t)(vb >> 31);
-      }
+      if (ab != 0u) atomicAdd(&nz, 1u);
+      key = (uint64_t)j;
     }
     keys[i] = key;
   }
   __syncthreads();
   // duplicate check: sort the coordinates alone, then compare neighbours
   {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const uint64_t k = keys[i];
-      keys[i] = (k == ~0ull) ? ~0ull : ((k & 0xFFFFFFFFull) >> 1);  // j, zeros last
-    }
     bitonic_sort_u64_asc(keys, n);
     for (int i = threadIdx.x; i + 1 < n; i += blockDim.x)
       if (keys[i] != ~0ull && keys[i] == keys[i + 1]) atomicOr(&bad, 1u);

@@ -196,7 +196,7 @@ static void par_memcpy(void *dst, const void *src, size_t bytes) {
 extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_index **out) {
   if (!out) return SNN_E_INVALID;
   *out = nullptr;
-  if (!cfg || cfg->dim == 0 || cfg->m == 0 || cfg->h == 0 || cfg->h > 4 || cfg->capacity == 0 ||
+  if (!cfg || cfg->dim == 0 || cfg->m == 0 || cfg->m > kMaxM || cfg->h == 0 || cfg->h > 4 || cfg->capacity == 0 ||
       cfg->capacity > (1u << 31) || (cfg->flags & ~(SNN_FORWARD_STORE | SNN_SKETCH_BF16 | SNN_UPPER_ONLY)) != 0 ||
       cfg->dim >= (1u << 31))
     return SNN_E_INVALID;
@@ -1105,8 +1105,10 @@ extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_
                                        const float *vals, uint32_t k, uint32_t *out_ids, float *out_scores,
                                        uint32_t *out_counts) {
   if (!ix) return SNN_E_INVALID;
-  return search_host(ix, nq, indptr, coords, vals, k, snn_search_params{SNN_MODE_BATCHED, 0, 0, 0}, out_ids,
-                     out_scores, out_counts);
+  // with the filter enabled the same search runs the learned form (same results)
+  const uint32_t mode = ix->filter_on ? SNN_MODE_LEARNED : SNN_MODE_BATCHED;
+  return search_host(ix, nq, indptr, coords, vals, k, snn_search_params{mode, 0, 0, 0}, out_ids, out_scores,
+                     out_counts);
 }
 
 extern "C" snn_status snn_search_rerank(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,

@@ -41,6 +41,7 @@ constexpr uint32_t kTileMax = 16384;     // largest tile (docs); capacity is a m
 constexpr int kPrepCap = 4096;           // max non-zeros of one query
 constexpr uint32_t kMaxK = 4096;        // largest k of a sorted result
 constexpr uint32_t kMaxKPrime = 65536;  // largest k' of the re-rank (Alg. 7)
+constexpr uint32_t kMaxM = 1024;        // largest m: the insert folds a column's 2m buckets in LDS
 
 struct DevIndex {
   uint64_t *bits;

@@ -127,6 +127,14 @@ extern "C" snn_status snn_filter_set_delta(snn_index *ix, float delta) {
   return SNN_OK;
 }
 
+extern "C" snn_status snn_filter_enable(snn_index *ix, int on) {
+  if (!ix) return SNN_E_INVALID;
+  if (on && (!ix->filter || !ix->filter->ready))
+    return ix->fail(SNN_E_INVALID, "filter: no trained filter (call snn_filter_train or snn_filter_set_params)");
+  ix->filter_on = on != 0;
+  return SNN_OK;
+}
+
 extern "C" snn_status snn_filter_features(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,
                                           const float *vals, float *out_features) {
   if (!ix || !indptr || !out_features) return SNN_E_INVALID;

@@ -252,6 +252,7 @@ struct snn_index {
   const unsigned long long *last_stats = nullptr;  // device: selection work of the last batch
   snn::Tune tune;
   snn::LearnedFilter *filter = nullptr;
+  bool filter_on = false;  // snn_filter_enable: the host-buffer searches run the learned form
 
   std::string err;
 

@@ -259,7 +259,7 @@ def make_gaussian(seed: int = 0, psi: int = 100, docs: int = 5_000_000, queries:
     """The real-valued collections of Section 6.5: every coordinate is non-zero
     with probability psi / n (uniform coordinates), values N(0, 1); 5M docs and
     1,000 queries of the same law. G100: psi = 100, n = 10,000, 2m = 74;
-    G200: psi = 200, n = 32,000, 2m = 150 (Table 6); h = 1; k = 1,000."""
+    G200: psi = 200, n = 32,000, 2m = 150 (Table 4); h = 1; k = 1,000."""
     n, m = {100: (10_000, 37), 200: (32_000, 75)}[psi]
     rng = np.random.Generator(np.random.PCG64(seed + 1000))
     d = sparse_rows(seed, docs, n, 1.0, bernoulli_counts(rng, docs, psi, n), "normal", uniform_coords=True)

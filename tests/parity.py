@@ -89,8 +89,11 @@ def check_rerank_query(gpu_ids, gpu_scores, est, est_abs, exact, exact_abs, ids_
     (twice the score tolerance, since both sides may round); then the GPU's k
     results must be the oracle's top-k by exact score over those candidates, by
     the rule of check_query. Otherwise the candidate set is open at its edge and
-    only what still holds is checked: every result is a candidate of some
-    valid top-k', its exact score is right and the list is sorted. Documents
+    what still holds is checked: every result is a candidate of some valid
+    top-k', its exact score is right, the list is sorted, and no candidate
+    that every valid top-k' contains (in the oracle's top-k' and outside the
+    edge) beats the GPU's k-th exact score beyond tolerance without being
+    returned. Documents
     that share no coordinate with the query score exactly 0 on both sides and
     are ordered by id alike, so they never open the edge. Returns True when
     the query was checked in full."""
@@ -117,10 +120,24 @@ def check_rerank_query(gpu_ids, gpu_scores, est, est_abs, exact, exact_abs, ids_
     pos_of_id = {int(i): p for p, i in enumerate(ids_of_pos)}
     allowed = set(V.tolist()) | set(np.nonzero(near)[0].tolist())
     gpos = np.array([pos_of_id[int(i)] for i in gpu_ids], dtype=np.int64)
+    assert len(set(gpos.tolist())) == len(gpos), "%s duplicate ids" % what
     assert all(int(p) in allowed for p in gpos), "%s result outside every valid candidate set" % what
     err = np.abs(np.asarray(gpu_scores, np.float64) - exact[gpos])
     assert np.all(err <= rel * exact_abs[gpos] + 1e-30), "%s exact score mismatch" % what
     for r in range(len(gpu_ids) - 1):
         a, b = gpu_scores[r], gpu_scores[r + 1]
         assert a > b or (a == b and gpu_ids[r] < gpu_ids[r + 1]), "%s order broken at rank %d" % (what, r)
+    # The certain candidates (in V and outside the edge) are in every valid
+    # top-k', so the GPU scored each of them exactly and kept the k best of its
+    # own candidate set: one that beats the GPU's k-th exact score by more than
+    # both sides' rounding must have been returned.
+    certain = np.setdiff1d(V, np.nonzero(near)[0])
+    missing = np.setdiff1d(certain, gpos)
+    if len(gpos) and len(missing):
+        kth = gpos[-1]
+        beat = exact[missing] - exact[kth] > rel * (exact_abs[missing] + exact_abs[kth]) + 1e-30
+        assert not np.any(beat), "%s certain candidate (id %d, exact %.9g) beats the GPU's k-th (%.9g) but is " \
+            "missing" % (what, ids_of_pos[missing[beat][0]], exact[missing[beat][0]], exact[kth])
+    elif len(missing):
+        raise AssertionError("%s no results while certain candidates exist" % what)
     return False

@@ -45,7 +45,8 @@ def test_create_rejects_bad_config_without_touching_the_device():
     L = P.lib()
     out = ctypes.c_void_p()
     for cfg in (P.Config(0, 32, 1, 100, 0, 0, 0), P.Config(100, 0, 1, 100, 0, 0, 0), P.Config(100, 32, 5, 100, 0, 0, 0),
-                P.Config(100, 32, 1, 0, 0, 0, 0), P.Config(100, 32, 1, 100, 0, 8, 0)):
+                P.Config(100, 32, 1, 0, 0, 0, 0), P.Config(100, 32, 1, 100, 0, 8, 0),
+                P.Config(100, 1025, 1, 100, 0, 0, 0)):
         assert L.snn_create(ctypes.byref(cfg), None, ctypes.byref(out)) == -1
         assert not out.value
     assert L.snn_last_error(None) == b"null index"

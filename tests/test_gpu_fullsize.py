@@ -81,7 +81,9 @@ def test_splade_1m_rerank_sampled_queries(splade1m):
         c = int(cnt[qi])
         full += parity.check_rerank_query(ids[qi][:c], sc[qi][:c], est, ea, ex, xa, ids_of_pos, 10, 1000,
                                           what="1M rerank q%d" % qi)
-    assert full >= SAMPLE // 2
+    # 6 of the 8 sampled queries have their k'-th estimate separated from the
+    # next (fixed by the oracle's scores alone) and are checked in full
+    assert full == 6, full
 
 
 def test_batch_4m_sampled_queries():
@@ -101,3 +103,56 @@ def test_batch_4m_sampled_queries():
     rows = [int(np.argmin(nnz)), int(np.argmax(nnz))] + list(np.random.default_rng(4).choice(w.queries.rows, 4,
                                                                                              replace=False))
     _check_sample(ora, w.queries, ids, sc, cnt, 100, rows, "4M k=100")
+
+
+def test_serving_8m_capacity_sampled_searches():
+    """The serving workload's shape: capacity 8,000,000 slots, 4,000,000
+    prefilled documents of the small-index law, a trace of searches (k in
+    {10, 100, 1000}), inserts and deletes run with continuous batching in the
+    launch configuration the benchmark uses. Twelve sampled searches (four of
+    each k) are checked against the FP64 oracle on the live set at their own
+    position in the trace."""
+    import paper_2301_10622_amd as P
+
+    prefill = 4_000_000
+    docs = gen.small_docs(0, prefill)
+    ix = P.Index(1000, 32, 1, capacity=8_000_000, hash_seed=0)
+    P.load_docs(ix, docs)
+    sq = gen.serving_queries(7, 1024)
+    ix.autotune(*_dev(sq), 100, total=int(sq.nnz))
+    tr = gen.serving_trace(11, 3000, np.arange(prefill), 10_000_000, 1e9, ks=(10, 100, 1000))
+    csr = gen.trace_csr(tr)
+    res_ids, res_sc, res_cnt, lat, rep = ix.serve(tr["kind"], tr["t"], tr["ids"], tr["k"], csr.indptr, csr.coords,
+                                                  csr.vals, max_batch=1024, max_inflight=3, streams=3,
+                                                  realtime=False, budget_bytes=8 << 30)
+    kind = tr["kind"]
+    sreq = np.nonzero(kind == 0)[0]
+    assert rep["searches"] == len(sreq) and rep["rejected"] == 0 and rep["max_inflight_seen"] >= 2
+    assert ix.live_count == prefill + int((kind == 1).sum()) - int((kind == 2).sum())
+    ix.close()
+    # one oracle index over every vector the trace ever holds: the prefill
+    # (ids 0 .. prefill - 1), then the inserted vectors in trace order; a
+    # search sees those inserted before it and not deleted before it
+    ins = np.nonzero(kind == 1)[0]
+    both = gen.CSR(np.concatenate([docs.indptr, docs.indptr[-1] + np.cumsum(np.diff(csr.indptr)[ins])]),
+                   np.concatenate([docs.coords] + [csr.row(r)[0] for r in ins]).astype(np.uint32),
+                   np.concatenate([docs.vals] + [csr.row(r)[1] for r in ins]).astype(np.float32))
+    ids = np.concatenate([np.arange(prefill), tr["ids"][ins]]).astype(np.uint32)
+    pos_of_id = {int(i): p for p, i in enumerate(ids)}
+    ora = O.Index(both, 1000, 32, 1, 0, ids=ids)
+    rng = np.random.default_rng(12)
+    pick = []
+    for k in (10, 100, 1000):
+        cand = np.nonzero(tr["k"][sreq] == k)[0]
+        pick += sorted(rng.choice(cand, 4, replace=False).tolist())
+    for i in pick:
+        r = int(sreq[i])
+        live = np.zeros(len(ids), bool)
+        live[:prefill] = True
+        live[prefill:] = ins < r
+        for d in np.nonzero((kind[:r] == 2))[0]:
+            live[pos_of_id[int(tr["ids"][d])]] = False
+        s, a = ora.score_all(*csr.row(r))
+        c = int(res_cnt[i])
+        parity.check_query(res_ids[i][:c], res_sc[i][:c], s, a, pos_of_id, ids.astype(np.int64), int(tr["k"][r]),
+                           live=live, what="serving 8M search %d (request %d, k=%d)" % (i, r, tr["k"][r]))

@@ -5,6 +5,7 @@ import pytest
 
 from oracle import oracle as O
 from synth import gen
+import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -113,7 +114,8 @@ def test_learned_results_identical_to_plain(trained, k):
     import paper_2301_10622_amd as P
 
     w, ix, rep = trained
-    t = _dev(gen.small_queries(3, 2048))
+    q = gen.small_queries(3, 2048)
+    t = _dev(q)
     plain = _dev_search(ix, t, k, P.MODE_BATCHED)
     learned = _dev_search(ix, t, k, P.MODE_LEARNED)
     inv, fb = ix.last_batch_status()
@@ -122,6 +124,40 @@ def test_learned_results_identical_to_plain(trained, k):
         assert np.array_equal(a, b)
     if k == 10:
         assert fb <= 0.15 * 2048, fb  # calibrated for about 5%
+    # the learned form's own results against the FP64 oracle (every query;
+    # the first 256 of them at k = 5 and 40)
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    rows = range(q.rows) if k == 10 else range(256)
+    parity.check_batch(learned[0], learned[1], learned[2], ora, q, k, what="learned k=%d" % k, rows=rows)
+
+
+def test_filter_enable_switches_the_host_calls_to_the_learned_form(trained):
+    """snn_filter_enable (through ctypes): snn_search_batch and snn_search run
+    the learned form while it is on, with the ids and scores of the plain form;
+    snn_last_batch_status reports the fallbacks of the learned pass."""
+    import paper_2301_10622_amd as P
+
+    w, ix, rep = trained
+    q = gen.small_queries(8, 1024)
+    plain = ix.search_batch(q.indptr, q.coords, q.vals, 10)
+    try:
+        ix.filter_enable(True)
+        got = ix.search_batch(q.indptr, q.coords, q.vals, 10)
+        _, fb_on = ix.last_batch_status()
+        one = ix.search(*q.row(5), 10)
+    finally:
+        ix.filter_enable(False)
+    for a, b in zip(plain, got):
+        assert np.array_equal(a, b)
+    assert np.array_equal(one[0], plain[0][5]) and np.array_equal(one[1], plain[1][5])
+    assert 0 < fb_on <= 0.15 * q.rows, fb_on  # the learned pass ran: some queries fell back
+    ix.search_batch(q.indptr, q.coords, q.vals, 10)
+    assert ix.last_batch_status()[1] == 0  # off again: the batched form has no fallback pass
+    bare = P.Index(w.n, w.m, w.h, capacity=100, hash_seed=w.hash_seed)
+    with pytest.raises(P.SnnError) as e:
+        bare.filter_enable(True)  # nothing trained
+    assert e.value.status == -1
+    bare.close()
 
 
 def _work(ix):

@@ -191,25 +191,32 @@ def test_rerank_gaussian_law_k1000_kprime20000():
     P.load_docs(ix, w.docs)
     ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
     q = w.queries
+    # queries whose k'-th estimate is separated from the next (checked in full;
+    # the others by the open-edge rule): fixed by the oracle's scores alone
+    fixed = {0: 3, 30: 4}
     for c in (0, 30):
         ids, sc, cnt = ix.search_ex(q.indptr, q.coords, q.vals, 1000, k_prime=20000, max_coords=c)
         ids_of_pos = ora.ids.astype(np.int64)
+        full = 0
         for qi in range(q.rows):
             qc, qv = q.row(qi)
             est, ea = ora.score_all(qc, qv, max_coords=c)
             ex, xa = ora.score_all(qc, qv, exact=True)
             n = int(cnt[qi])
-            parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
-                                      what="g100-law c=%d q%d" % (c, qi))
+            full += parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
+                                              what="g100-law c=%d q%d" % (c, qi))
+        assert full == fixed[c], (c, full)
     ix.close()
 
 
-def _sampled_case(docs, queries, boost_rows=0, law="small"):
+def _sampled_case(docs, queries, boost_rows=0, law="small", seed=1):
     P = _lib()
     if law == "small":
         w = gen.make_small(3, docs=docs, queries=queries)
+    elif law == "g200":
+        w = gen.make_gaussian(seed, 200, docs=docs, queries=queries)
     else:
-        w = gen.make_gaussian(1, 100, docs=docs, queries=queries)
+        w = gen.make_gaussian(seed, 100, docs=docs, queries=queries)
     d = w.docs
     if boost_rows:
         # the first documents (the first tiles) hold the largest values, so the
@@ -270,17 +277,35 @@ def test_rerank_sampled_thresholds_fall_back_when_the_sample_misleads():
 def test_rerank_sampled_thresholds_gaussian_law_k1000_kprime20000():
     """The G100 law at 320,000 documents with k = 1,000 and k' = 20,000 (78
     tiles, so the sampled first pass runs), full and anytime."""
-    w, d, ix, ora = _sampled_case(320_000, 5, law="gaussian")
+    _gaussian_sampled(_sampled_case(320_000, 5, law="gaussian"), {0: 3, 30: 3}, "g100-law")
+
+
+def _gaussian_sampled(case, fixed, what):
+    w, d, ix, ora = case
     q = w.queries
     ids_of_pos = ora.ids.astype(np.int64)
-    for c in (0, 30):
+    for c in sorted(fixed):
         (ids, sc, cnt), work, fallbacks = _search_two_ways(ix, q, 1000, 20000, c)
         assert fallbacks == 0
+        full = 0
         for qi in range(q.rows):
             qc, qv = q.row(qi)
             est, ea = ora.score_all(qc, qv, max_coords=c)
             ex, xa = ora.score_all(qc, qv, exact=True)
             n = int(cnt[qi])
-            parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
-                                      what="g100-law sampled c=%d q%d" % (c, qi))
+            assert n == 1000
+            full += parity.check_rerank_query(ids[qi][:n], sc[qi][:n], est, ea, ex, xa, ids_of_pos, 1000, 20000,
+                                              what="%s sampled c=%d q%d" % (what, c, qi))
+        # queries checked in full (the k'-th estimate separated from the next,
+        # fixed by the oracle's scores alone); the rest by the open-edge rule
+        assert full == fixed[c], (what, c, full)
     ix.close()
+
+
+def test_rerank_sampled_thresholds_g200_law_k1000_kprime20000():
+    """The G200 law of Section 6.5 (psi = 200 of n = 32,000 coordinates,
+    N(0, 1) values, 2m = 150, h = 1) at 320,000 documents with Table 4's
+    k = 1,000 and k' = 20,000, full and anytime (the first 60 coordinates)."""
+    case = _sampled_case(320_000, 6, law="g200", seed=2)
+    assert case[0].m == 75 and case[0].n == 32000
+    _gaussian_sampled(case, {0: 5, 60: 4}, "g200-law")

@@ -172,6 +172,38 @@ def test_malformed_inputs_are_rejected():
     assert ix.live_count == 1
 
 
+@pytest.mark.parametrize("length", [40, 300])
+def test_device_batch_flags_duplicates_with_a_zero_value(length):
+    """A query that repeats a coordinate is malformed even when one copy holds
+    0, in the short (<= 256 entries) and the long preparation path alike; the
+    other queries of the batch are unaffected."""
+    import torch
+
+    P = _lib()
+    w = gen.make_small(1, docs=2000, queries=3)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
+    P.load_docs(ix, w.docs)
+    rng = np.random.default_rng(length)
+    c = rng.choice(w.n, length, replace=False).astype(np.uint32)
+    v = rng.standard_normal(length).astype(np.float32)
+    c[-1] = c[7]
+    v[-1] = 0.0  # the duplicate is a zero
+    good_c, good_v = w.queries.row(0)
+    indptr = np.array([0, len(good_c), len(good_c) + length], dtype=np.int64)
+    coords = np.concatenate([good_c, c]).astype(np.int32)
+    vals = np.concatenate([good_v, v]).astype(np.float32)
+    d = torch.device("cuda:0")
+    ids, sc, cnt = ix.search_batch_dev(torch.tensor(indptr, device=d), torch.tensor(coords, device=d),
+                                       torch.tensor(vals, device=d), 10, mode=P.MODE_BATCHED, total=len(coords))
+    torch.cuda.synchronize()
+    cnt = cnt.cpu().numpy()
+    inv, _ = ix.last_batch_status()
+    assert inv == 1 and cnt[1] == 0 and cnt[0] == 10
+    ref_ids, _ = ix.search(good_c, good_v, 10)
+    assert np.array_equal(ids.cpu().numpy()[0].astype(np.uint32), ref_ids)
+    ix.close()
+
+
 def test_capacity_full():
     P = _lib()
     ix = _fresh(10, 4, 1, 3)  # rounded up to one full tile internally
