@@ -148,6 +148,30 @@ snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indp
                                 const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode, uint32_t *out_ids,
                                 float *out_scores, uint32_t *out_counts, void *stream);
 
+/* Allocation-free form of snn_search_batch_dev, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Arguments, layouts, ownership and results
+ * are those of snn_search_batch_dev with mode SNN_MODE_PLAIN or
+ * SNN_MODE_BATCHED. The batch's workspace (prepared query entries, per-query
+ * thresholds and counters, work queues, tile candidates) is carved from one
+ * array of SNN_NOALLOC_SCRATCH_BYTES of device memory that the library holds
+ * on each device it runs on until the process ends; the call allocates
+ * nothing and uses no HIP graph (its kernels are enqueued one by one, so a
+ * capturing caller records them). Every call on one device shares that array
+ * and overwrites the previous call's contents: calls that overlap on one
+ * device (concurrent streams, threads) race and must be serialised by the
+ * caller; the results of a call stay valid, they are in the caller's buffers.
+ * The device current at the call must be the one current at snn_create.
+ * Errors: SNN_E_INVALID (as snn_search_batch_dev; SNN_MODE_LEARNED; another
+ * device current; a batch whose workspace exceeds the array: about
+ * nq x tiles x min(k, tile) x 8 bytes of tile candidates plus 12 bytes per
+ * query entry and a few words per query, with tiles = ceil(slots used / tile)
+ * and a tile of 256 R slots, R from the schedule), SNN_E_DEVICE. */
+#define SNN_NOALLOC_SCRATCH_BYTES (64ull << 20)
+snn_status snn_search_batch_dev_noalloc(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                        const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode,
+                                        uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream);
+
 /* Options of one batch search (all the forms above in one call):
  *   mode        SNN_MODE_PLAIN, SNN_MODE_BATCHED or SNN_MODE_LEARNED
  *   k_prime     0: ranking by the Sinnamon scores (Alg. 7 with k' = k, i.e.

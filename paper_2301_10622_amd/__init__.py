@@ -39,7 +39,9 @@ EXPORTS = [
     "snn_profile_read_updates", "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
     "snn_filter_set_params", "snn_filter_set_delta", "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run",
+    "snn_search_batch_dev_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MLP_PARAMS = 49537
 
 
@@ -135,6 +137,7 @@ def lib():
         L.snn_search.argtypes = [P, u32, P, P, u32, P, P, P]
         L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
         L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
+        L.snn_search_batch_dev_noalloc.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
         L.snn_search_rerank.argtypes = [P, u32, P, P, P, u32, u32, P, P, P]
         L.snn_search_ex.argtypes = [P, u32, P, P, P, u32, P, P, P, P]
@@ -169,7 +172,7 @@ def lib():
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_profile_read_updates", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
-                     "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run"):
+                     "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run", "snn_search_batch_dev_noalloc"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -354,6 +357,28 @@ class Index:
         assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
         self._check(lib().snn_search_batch_dev(self._h, nq, _tp(indptr), int(total), _tp(coords), _tp(vals), k, mode,
                                                _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
+        return ids, sc, cnt
+
+    def search_batch_dev_noalloc(self, indptr, coords, vals, k: int, mode: int = MODE_BATCHED, out=None,
+                                 stream=None, total: Optional[int] = None):
+        """search_batch_dev with the workspace in the library's fixed device
+        array (snn_search_batch_dev_noalloc): nothing is allocated by the
+        call. `out` (ids, scores, counts) must be given when the caller
+        cannot allocate either."""
+        nq = indptr.numel() - 1
+        if total is None:
+            total = int(coords.numel())
+        dev = indptr.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev),
+                   torch.empty(nq, dtype=torch.int32, device=dev))
+        ids, sc, cnt = out
+        assert indptr.dtype == torch.int64 and coords.dtype == torch.int32 and vals.dtype == torch.float32
+        assert indptr.is_contiguous() and coords.is_contiguous() and vals.is_contiguous()
+        assert ids.shape == (nq, k) and sc.shape == (nq, k) and cnt.shape == (nq,)
+        self._check(lib().snn_search_batch_dev_noalloc(self._h, nq, _tp(indptr), int(total), _tp(coords), _tp(vals),
+                                                       k, mode, _tp(ids), _tp(sc), _tp(cnt), _stream_handle(stream)))
         return ids, sc, cnt
 
     def last_batch_status(self):

@@ -206,6 +206,10 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   ix->cap = (uint32_t)(((uint64_t)cfg->capacity + kTileMax - 1) / kTileMax * kTileMax);
   ix->W = ix->cap / 64;
   ix->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&ix->device) != hipSuccess) {
+    delete ix;
+    return SNN_E_DEVICE;
+  }
   DevIndex &d = ix->dev;
   d.dim = cfg->dim;
   d.m = cfg->m;
@@ -570,8 +574,12 @@ extern "C" snn_status snn_delete(snn_index *ix, uint32_t id) { return snn_delete
 // Device workspace for one batch: prepared entries, per-query state, tile
 // candidates. Laid out in one allocation.
 // kt: candidates a tile keeps per query; kprime > 0: the re-rank's buffers too.
+// ext (nullable): a caller region of ext_bytes (256-byte aligned) that holds
+// every buffer instead, so that nothing is allocated; a batch that needs more
+// is rejected.
 snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime,
-                                        uint32_t ksample, SearchWs &w, Workspace &W, hipStream_t stream) {
+                                        uint32_t ksample, SearchWs &w, Workspace &W, hipStream_t stream, char *ext,
+                                        size_t ext_bytes) {
   const uint32_t h = cfg.h;
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   size_t o = 0;
@@ -594,9 +602,35 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   const size_t o_ssi = o; o += al((size_t)nq * ks * 4);
   const size_t o_sss = o; o += al((size_t)nq * ks * 4);
   const size_t o_ssc = o; o += al((size_t)nq * 4);
-  HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
-  HIP_TRY(this, W.cand.ensure((size_t)nq * tiles * kt * 8 + 64, stream), "candidate buffer");
-  char *p = (char *)W.ws.p;
+  const size_t cand_bytes = (size_t)nq * tiles * kt * 8 + 64;
+  const size_t kp = kprime;
+  const size_t cslot_bytes = kprime ? (size_t)nq * tiles * kt * 4 + 64 : 0;
+  const size_t o_keys = kprime ? al((size_t)nq * kp * 12 + (size_t)nq * 4) : 0;
+  const size_t rr_bytes = kprime ? o_keys + (size_t)nq * kp * 8 + 256 : 0;
+  char *p, *pc, *ps = nullptr, *pr = nullptr;
+  if (ext) {
+    const size_t need = al(o) + al(cand_bytes) + al(cslot_bytes) + al(rr_bytes);
+    if (need > ext_bytes)
+      return fail(SNN_E_INVALID, "search: the batch needs %zu bytes of workspace, more than the %zu of the region",
+                  need, ext_bytes);
+    p = ext;
+    pc = p + al(o);
+    if (kprime) {
+      ps = pc + al(cand_bytes);
+      pr = ps + al(cslot_bytes);
+    }
+  } else {
+    HIP_TRY(this, W.ws.ensure(o, stream), "search workspace");
+    HIP_TRY(this, W.cand.ensure(cand_bytes, stream), "candidate buffer");
+    if (kprime) {
+      HIP_TRY(this, W.cslot.ensure(cslot_bytes, stream), "candidate slots");
+      HIP_TRY(this, W.rr.ensure(rr_bytes, stream), "re-rank candidates");
+      ps = (char *)W.cslot.p;
+      pr = (char *)W.rr.p;
+    }
+    p = (char *)W.ws.p;
+    pc = (char *)W.cand.p;
+  }
   w.cnt = (uint32_t *)(p + o_cnt);
   w.status = (uint32_t *)(p + o_status);
   w.thr = (uint32_t *)(p + o_thr);
@@ -615,21 +649,17 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   w.ss_ids = (uint32_t *)(p + o_ssi);
   w.ss_sc = (float *)(p + o_sss);
   w.ss_cnt = (uint32_t *)(p + o_ssc);
-  w.cand = (uint64_t *)W.cand.p;
+  w.cand = (uint64_t *)pc;
   w.cslot = w.rr_ids = w.rr_slot = w.rr_cnt = nullptr;
   w.rr_sc = nullptr;
   w.rk = nullptr;
   if (kprime) {
-    const size_t kp = kprime;
-    HIP_TRY(this, W.cslot.ensure((size_t)nq * tiles * kt * 4 + 64, stream), "candidate slots");
-    const size_t o_keys = al((size_t)nq * kp * 12 + (size_t)nq * 4);
-    HIP_TRY(this, W.rr.ensure(o_keys + (size_t)nq * kp * 8 + 256, stream), "re-rank candidates");
-    w.cslot = (uint32_t *)W.cslot.p;
-    w.rr_ids = (uint32_t *)W.rr.p;
+    w.cslot = (uint32_t *)ps;
+    w.rr_ids = (uint32_t *)pr;
     w.rr_sc = (float *)(w.rr_ids + (size_t)nq * kp);
     w.rr_slot = (uint32_t *)(w.rr_sc + (size_t)nq * kp);
     w.rr_cnt = w.rr_slot + (size_t)nq * kp;
-    w.rk = (uint64_t *)((char *)W.rr.p + o_keys);
+    w.rk = (uint64_t *)(pr + o_keys);
   }
   return SNN_OK;
 }
@@ -913,7 +943,7 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
     }
   }
   return prepare_workspace(nq, total - o.ebase, p.kt, p.tiles, o.rerank_k ? k : 0, p.k_s, p.w, o.wsp ? *o.wsp : wsp,
-                           s);
+                           s, o.ext_ws, o.ext_ws_bytes);
 }
 
 snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
@@ -1099,6 +1129,31 @@ static snn_status search_dev_entry(snn_index *ix, uint32_t nq, const uint64_t *i
   hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
   // no query holds more entries than the batch (the host does not read indptr)
   return search_dev(ix, nq, indptr, total, coords, vals, k, p, total, out_ids, out_scores, out_counts, s);
+}
+
+// The device-buffer search with every workspace buffer carved from the
+// caller's region `ext` of `ext_bytes`: no device allocation and no HIP graph
+// (the work is enqueued kernel by kernel, so a capturing caller records it).
+snn_status snn_search_dev_in_region(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                    const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode,
+                                    uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream,
+                                    char *ext, size_t ext_bytes) {
+  const snn_search_params p{mode, 0, 0, 0};
+  snn_status st = check_params(ix, k, p);
+  if (st != SNN_OK) return st;
+  if (mode == SNN_MODE_LEARNED)
+    return ix->fail(SNN_E_INVALID, "search: the allocation-free form runs SNN_MODE_PLAIN or SNN_MODE_BATCHED");
+  if (nq == 0) return ix->fail(SNN_E_INVALID, "search: nq must be > 0");
+  if (!indptr || !out_ids || !out_scores || !out_counts || (total && (!coords || !vals)))
+    return ix->fail(SNN_E_INVALID, "search: null pointer");
+  hipStream_t s = stream ? (hipStream_t)stream : ix->stream;
+  ix->last_nq = nq;
+  ix->last_mode = mode;
+  SearchOpts o;
+  o.ext_ws = ext;
+  o.ext_ws_bytes = ext_bytes;
+  o.no_graph = true;
+  return ix->run_search(nq, indptr, total, coords, vals, k, (int)mode, out_ids, out_scores, out_counts, s, o);
 }
 
 extern "C" snn_status snn_search_batch(snn_index *ix, uint32_t nq, const uint64_t *indptr, const uint32_t *coords,

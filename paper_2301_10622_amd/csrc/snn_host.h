@@ -96,6 +96,8 @@ struct SearchOpts {
   const uint32_t *qseq = nullptr;      // serving: per-query sequence numbers (snapshot visibility)
   uint64_t ebase = 0;                  // indptr value of the batch's first entry
   Workspace *wsp = nullptr;            // buffers (null: the index's own)
+  char *ext_ws = nullptr;              // caller region that holds every buffer instead (nothing allocated)
+  size_t ext_ws_bytes = 0;
   bool no_graph = false;
 };
 
@@ -197,6 +199,11 @@ struct GraphCache {
 }  // namespace snn
 
 void snn_filter_release(struct snn_index *ix);
+// Device-buffer search with the workspace in the caller's region (snn_api.cpp).
+snn_status snn_search_dev_in_region(struct snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
+                                    const uint32_t *coords, const float *vals, uint32_t k, uint32_t mode,
+                                    uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream,
+                                    char *ext, size_t ext_bytes);
 // Working state of the duplicate-coordinate check: a sort of the coordinates,
 // or, over many vectors of a moderate dimension, one stamp per coordinate (the
 // tag of the last vector that held it), so each vector costs O(nnz).
@@ -218,6 +225,7 @@ bool snn_check_vector(struct snn_index *ix, uint32_t nnz, const uint32_t *c, con
 struct snn_index {
   snn_config cfg{};
   uint32_t cap = 0, W = 0;
+  int device = -1;  // the device current at snn_create, which holds the index
   hipStream_t stream = nullptr;
   snn::DevIndex dev{};
   snn::DevForward fw{};  // forward store (SNN_FORWARD_STORE)
@@ -285,7 +293,7 @@ struct snn_index {
   snn_status upload_and_delete(const std::vector<uint32_t> &slots, const std::vector<uint64_t> &ptr,
                                const std::vector<uint32_t> &co, int clear_bits, int clear_live);
   snn_status prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt, uint32_t tiles, uint32_t kprime, uint32_t ksample,
-                               snn::SearchWs &w, snn::Workspace &W, hipStream_t s);
+                               snn::SearchWs &w, snn::Workspace &W, hipStream_t s, char *ext, size_t ext_bytes);
   snn_status enqueue_merge(const snn::SearchWs &w, const snn::MergeJob &j, hipStream_t s);
   snn_status plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c, const float *d_v,
                          uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, snn::SearchPlan &p,
