@@ -59,10 +59,16 @@ def main():
                     help="coordinate budgets of the anytime re-ranking forms (k' = 1000); empty to skip")
     ap.add_argument("--serving-ops", type=int, default=100_000)
     ap.add_argument("--plain-steps", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=64, help="queries checked against the oracle's Alg. 7")
+    ap.add_argument("--cpu-sample-one", type=int, default=64, help="queries timed on one host thread")
+    ap.add_argument("--cpu-reps", type=int, default=5, help="runs of the all-thread oracle timing (median)")
     ap.add_argument("--updates", type=int, default=131072,
                     help="documents deleted and re-inserted to time the update kernels (0: build only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="leave every coordinate in its bitmap container (no array containers)")
+    ap.add_argument("--schedule", default="",
+                    help="R,Q,grid,persistent: the batched schedule to use instead of autotuning (profiling runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -100,10 +106,19 @@ def main():
     torch.cuda.synchronize()
     ix.profile(True)
     t = time.time()
-    P.load_docs(ix, w.docs)
+    P.load_docs(ix, w.docs, compact=False)
     torch.cuda.synchronize()
     t_ins = time.time() - t
     build_upd = ix.profile_read_updates()
+    containers = {"compacted": not args.no_compact}
+    if not args.no_compact:
+        t = time.time()
+        ix.compact()
+        t_compact = time.time() - t
+        cls = ix.container_classes()
+        containers.update({"compaction_s": round(t_compact, 4), "array_coords": int(cls.sum()), "dim": w.n,
+                           "query_entries_with_arrays": round(float(cls[w.queries.coords].mean()), 4)})
+        log("compaction %.3fs: %d of %d coordinates with array containers" % (t_compact, int(cls.sum()), w.n))
     ix.profile(False)
     log("index built: %.2fs (%.0f docs/s through the host API; insert kernel %.2f ms for %d docs)" % (
         t_ins, w.docs.rows / t_ins, build_upd["insert_ms"], build_upd["insert_docs"]))
@@ -155,8 +170,13 @@ def main():
                "tile_kernel_ms_per_launch": kms / max(launches, 1), "tile_launches_per_step": launches / steps}
         return res, out
 
-    log("autotuning the schedule on the batch")
-    sched = ix.autotune(ip, qc, qv, args.k, total=total)
+    if args.schedule:
+        R, Q, grid, pers = [int(x) for x in args.schedule.split(",")]
+        ix.set_schedule(16, R, grid, bool(pers), Q)
+        sched = ix.schedule()
+    else:
+        log("autotuning the schedule on the batch")
+        sched = ix.autotune(ip, qc, qv, args.k, total=total)
     log("schedule: %s" % sched)
 
     forms = {}
@@ -241,7 +261,7 @@ def main():
         for vname, bf, up in (("bf16", True, False), ("upper_only", False, True), ("bf16_upper_only", True, True)):
             vx = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
                          forward_store=True, sketch_bf16=bf, upper_only=up)
-            P.load_docs(vx, w.docs)
+            P.load_docs(vx, w.docs, compact=not args.no_compact)
             vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]),
                             sched["qgroup"])
             r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2)}
@@ -295,6 +315,7 @@ def main():
         "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1),
         "update_kernels": updates,
         "host_api_search": host_api,
+        "containers": containers,
         "schedule": sched,
         "filters": filters,
     }
@@ -303,6 +324,9 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as O
 
+        # timed: every query of the batch on all host threads (median of
+        # cpu_reps runs) and a bounded sample on one thread (median of 3);
+        # recall over every query, the re-rank agreement on a sample
         S = min(args.cpu_sample, nq)
         sample = w.queries.take(range(S))
         log("oracle: building FP64 index")
@@ -310,56 +334,78 @@ def main():
         ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
         t_build = time.time() - t
         threads = O.max_threads()
-        log("oracle: index %.1fs; timing %d queries on %d threads" % (t_build, S, threads))
+        log("oracle: index %.1fs; timing %d queries on %d threads x %d runs" % (t_build, nq, threads, args.cpu_reps))
+        runs = []
+        for _ in range(args.cpu_reps):
+            t = time.perf_counter()
+            oids, osc, oab, ocnt = ora.search(w.queries, args.k, threads=threads)
+            runs.append(time.perf_counter() - t)
+        t_est = float(np.median(runs))
         t = time.perf_counter()
-        oids, osc, oab, ocnt = ora.search(sample, args.k, threads=threads)
-        t_est = time.perf_counter() - t
-        t = time.perf_counter()
-        eids, esc, _, ecnt = ora.search(sample, args.k, exact=True, threads=threads)
+        eids, esc, _, ecnt = ora.search(w.queries, args.k, exact=True, threads=threads)
         t_exact = time.perf_counter() - t
-        # the same estimate on one thread, over the first 16 queries of the sample
-        S1 = min(16, S)
-        t = time.perf_counter()
-        ora.search(w.queries.take(range(S1)), args.k, threads=1)
-        t_one = time.perf_counter() - t
-        gids = outs[(best, args.k)][0][:S].cpu().numpy().astype(np.int64)
-        gcnt = outs[(best, args.k)][2][:S].cpu().numpy()
+        S1 = min(args.cpu_sample_one, nq)
+        one = []
+        for _ in range(3):
+            t = time.perf_counter()
+            ora.search(w.queries.take(range(S1)), args.k, threads=1)
+            one.append(time.perf_counter() - t)
+        t_one = float(np.median(one))
+        gids = outs[(best, args.k)][0].cpu().numpy().astype(np.int64)
+        gcnt = outs[(best, args.k)][2].cpu().numpy()
         rec = []
         agree = []
-        for i in range(S):
+        for i in range(nq):
             g = set(gids[i][: gcnt[i]].tolist())
             rec.append(len(g & set(eids[i][: ecnt[i]].tolist())) / max(1, min(args.k, ecnt[i])))
             agree.append(len(g & set(oids[i][: ocnt[i]].tolist())) / max(1, ocnt[i]))
         result["recall_at_%d" % args.k] = round(float(np.mean(rec)), 4)
+        for fname, r in result["forms"].items():
+            if fname.endswith("_k%d" % args.k):
+                r["recall_at_%d" % args.k] = result["recall_at_%d" % args.k]
         for vname, r in variants_res.items():
             for form in ("batched_k10", "rerank_k1000_coords10"):
-                g_ids = outs[("variant", vname, form)][0][:S].cpu().numpy().astype(np.int64)
-                g_cnt = outs[("variant", vname, form)][2][:S].cpu().numpy()
+                g_ids = outs[("variant", vname, form)][0].cpu().numpy().astype(np.int64)
+                g_cnt = outs[("variant", vname, form)][2].cpu().numpy()
                 rr = [len(set(g_ids[i][: g_cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist()))
-                      / max(1, min(args.k, ecnt[i])) for i in range(S)]
+                      / max(1, min(args.k, ecnt[i])) for i in range(nq)]
                 r[form]["recall_at_%d" % args.k] = round(float(np.mean(rr)), 4)
-        # re-ranked forms: recall against exact brute force, agreement with the oracle's Alg. 7
+        # re-ranked forms: recall against exact brute force (every query),
+        # agreement with the oracle's Alg. 7 (the sample)
         for kp, c in variants:
             rids, _, _, rcnt = ora.rerank(sample, args.k, kp, threads=threads, max_coords=c)
-            g_ids = outs[("rerank", kp, c)][0][:S].cpu().numpy().astype(np.int64)
-            g_cnt = outs[("rerank", kp, c)][2][:S].cpu().numpy()
+            g_ids = outs[("rerank", kp, c)][0].cpu().numpy().astype(np.int64)
+            g_cnt = outs[("rerank", kp, c)][2].cpu().numpy()
             rr = [len(set(g_ids[i][: g_cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist()))
-                  / max(1, min(args.k, ecnt[i])) for i in range(S)]
+                  / max(1, min(args.k, ecnt[i])) for i in range(nq)]
             same = [np.array_equal(g_ids[i][: g_cnt[i]], rids[i][: rcnt[i]].astype(np.int64)) for i in range(S)]
             rerank[(kp, c)]["recall_at_%d" % args.k] = round(float(np.mean(rr)), 4)
             rerank[(kp, c)]["identical_to_oracle_alg7"] = round(float(np.mean(same)), 4)
             log("rerank k'=%d coords %s: recall@%d %.4f, identical to the oracle on %.0f%% of %d queries" % (
                 kp, c or "all", args.k, np.mean(rr), 100 * np.mean(same), S))
-        result["topk_agreement_with_oracle_estimate"] = round(float(np.mean(agree)), 4)
-        result["cpu_baseline"] = {"value": round(S / t_est, 2), "unit": "queries/s", "cores": threads,
+        # recall@100 of the k = 100 forms (identical results in every form)
+        ref100 = next(((n, 100) for n in ("batched", "plain", "learned") if (n, 100) in outs), None)
+        if ref100 and args.k != 100:
+            e100, _, _, c100 = ora.search(w.queries, 100, exact=True, threads=threads)
+            g_ids = outs[ref100][0].cpu().numpy().astype(np.int64)
+            g_cnt = outs[ref100][2].cpu().numpy()
+            r100 = float(np.mean([len(set(g_ids[i][: g_cnt[i]].tolist()) & set(e100[i][: c100[i]].tolist()))
+                                  / max(1, min(100, c100[i])) for i in range(nq)]))
+            for fname, r in result["forms"].items():
+                if fname.endswith("_k100"):
+                    r["recall_at_100"] = round(r100, 4)
+        result["cpu_baseline"] = {"value": round(nq / t_est, 2), "unit": "queries/s", "cores": threads,
                                   "kind": "oracle",
-                                  "sample": "first %d of the %d queries, k=%d, FP64 coordinate-at-a-time estimate "
-                                            "+ FindLargest; index build %.1fs excluded" % (S, nq, args.k, t_build),
-                                  "exact_brute_force_qps": round(S / t_exact, 2),
+                                  "sample": "all %d queries of the batch, k=%d, FP64 coordinate-at-a-time estimate "
+                                            "+ FindLargest, median of %d runs on %d threads; index build %.1fs "
+                                            "excluded" % (nq, args.k, args.cpu_reps, threads, t_build),
+                                  "runs_s": [round(x, 3) for x in runs],
+                                  "exact_brute_force_qps": round(nq / t_exact, 2),
                                   "single_thread_qps": round(S1 / t_one, 2),
+                                  "single_thread_sample": "first %d queries, median of 3 runs" % S1,
                                   "host": host_cpu()}
-        log("oracle: %.2f q/s (estimate), %.2f q/s (exact), %.2f q/s on one thread; recall@%d %.4f" % (
-            S / t_est, S / t_exact, S1 / t_one, args.k, result["recall_at_%d" % args.k]))
+        log("oracle: %.2f q/s (estimate, median of %d), %.2f q/s (exact), %.2f q/s on one thread; recall@%d %.4f" % (
+            nq / t_est, args.cpu_reps, nq / t_exact, S1 / t_one, args.k, result["recall_at_%d" % args.k]))
     if variants_res:
         result["sketch_variants"] = {v: {f: ({kk: (round(x, 4) if isinstance(x, float) else x) for kk, x in d.items()}
                                              if isinstance(d, dict) else d) for f, d in r.items()}
@@ -439,7 +485,7 @@ def update_kernels(P, np, ix, w, build, n_upd):
         sub = w.docs.take(range(n_upd))
         ix.profile(True)
         ix.delete_batch(ids)
-        P.load_docs(ix, sub, ids=ids)
+        P.load_docs(ix, sub, ids=ids, compact=False)
         u = ix.profile_read_updates()
         ix.profile(False)
         psi = nnz[:n_upd]
@@ -518,6 +564,17 @@ def measured_traffic(kernel, k):
     return rec["traffic_bytes_per_launch"] if k == 10 else None
 
 
+def recall_vs_exact(ora, queries, ids, cnt, k, threads):
+    """Mean recall@k of the GPU results (ids, counts: numpy rows of `queries`)
+    against the oracle's exact brute-force top-k (Eq. 2)."""
+    import numpy as np
+
+    eids, _, _, ecnt = ora.search(queries, k, exact=True, threads=threads)
+    r = [len(set(ids[i][: cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist())) / max(1, min(k, ecnt[i]))
+         for i in range(queries.rows)]
+    return float(np.mean(r))
+
+
 def _rounded(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
@@ -529,7 +586,7 @@ def batch_4m(args, dev, P, gen, np, torch):
     w = gen.make_batch(0)
     log("batch4m: generated %d docs / %d queries in %.1fs" % (w.docs.rows, w.queries.rows, time.time() - t))
     ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=torch.cuda.current_stream())
-    P.load_docs(ix, w.docs)
+    P.load_docs(ix, w.docs, compact=not args.no_compact)
     up = lambda q: (torch.tensor(q.indptr, dtype=torch.int64, device=dev),
                     torch.tensor(q.coords.astype(np.int32), device=dev), torch.tensor(q.vals, device=dev))
     et = up(w.queries)
@@ -555,6 +612,21 @@ def batch_4m(args, dev, P, gen, np, torch):
         log("batch4m %-8s %9.3f ms/step %10.0f q/s alg %.0f GB/s" % (name, ms, nq / (ms / 1000), ab / (ms / 1000) / 1e9))
     res["batched_over_plain"] = round(res["batched"]["qps"] / res["plain"]["qps"], 2)
     ix.close()
+    # recall@100 against exact brute force on a seeded sample of the batch
+    # (plain and batched return identical results)
+    from oracle import oracle as O
+
+    S = 64
+    rows = np.sort(np.random.default_rng(5).choice(nq, S, replace=False))
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    g_ids = out[0].cpu().numpy().astype(np.int64)[rows]
+    g_cnt = out[2].cpu().numpy()[rows]
+    rec = round(recall_vs_exact(ora, w.queries.take(rows), g_ids, g_cnt, k, O.max_threads()), 4)
+    for name in ("plain", "batched"):
+        res[name]["recall_at_100"] = rec
+    res["recall_sample"] = "%d seeded queries of the batch" % S
+    log("batch4m recall@100 %.4f (%d queries)" % (rec, S))
+    del ora
     return res
 
 
@@ -574,7 +646,7 @@ def paper_gaussian(args, dev, P, gen, np, torch, psi):
     stream = torch.cuda.current_stream()
     ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream, forward_store=True)
     t = time.time()
-    P.load_docs(ix, w.docs)
+    P.load_docs(ix, w.docs, compact=not args.no_compact)
     torch.cuda.synchronize()
     t_ins = time.time() - t
     k, kp, B = 1000, 20000, 200
@@ -664,7 +736,7 @@ def serving_8m(args, dev, P, gen, np, torch):
     docs = gen.small_docs(0, 4_000_000)
     log("serving: generated prefill in %.1fs" % (time.time() - t))
     ix = P.Index(1000, 32, 1, capacity=8_000_000, hash_seed=0, stream=torch.cuda.current_stream())
-    P.load_docs(ix, docs)
+    P.load_docs(ix, docs, compact=not args.no_compact)
     ops = args.serving_ops
     res = {"workload": "serving capacity 8M, 4M prefill, %d ops, 85/10/5 search/insert/delete" % ops}
     # the batched schedule, tuned on 1,024 queries of the serving law at k = 100
@@ -675,6 +747,19 @@ def serving_8m(args, dev, P, gen, np, torch):
     del et
     log("serving: schedule %s" % res["schedule"])
     budget = 8 << 30
+    # recall@k of the serving index against exact brute force, on the
+    # prefilled state, for 64 queries of the serving law at each k of the mix
+    from oracle import oracle as O
+
+    rq = gen.serving_queries(9, 64)
+    ora = O.Index(docs, 1000, 32, 1, 0)
+    res["recall_prefill"] = {}
+    for kk in (10, 100, 1000):
+        g_ids, _, g_cnt = ix.search_batch(rq.indptr, rq.coords, rq.vals, kk)
+        res["recall_prefill"]["recall_at_%d" % kk] = round(
+            recall_vs_exact(ora, rq, g_ids.astype(np.int64), g_cnt, kk, O.max_threads()), 4)
+    del ora
+    log("serving recall on the prefilled index (64 queries): %s" % res["recall_prefill"])
 
     live = {"ids": np.arange(docs.rows, dtype=np.int64)}
 
@@ -709,7 +794,7 @@ def small_learned(args, dev, P, gen, np, torch):
     labelled by the plain method, 8,192 evaluation queries, k = 10."""
     w = gen.make_small(0)
     ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=torch.cuda.current_stream())
-    P.load_docs(ix, w.docs)
+    P.load_docs(ix, w.docs, compact=not args.no_compact)
     tq = gen.small_queries(2, 200_000)
     eq = gen.small_queries(3, 8192)
     up = lambda q: (torch.tensor(q.indptr, dtype=torch.int64, device=dev),
@@ -743,6 +828,15 @@ def small_learned(args, dev, P, gen, np, torch):
     res["learned_over_batched"] = round(res["learned"]["qps"] / res["batched"]["qps"], 3)
     res["learned_over_plain"] = round(res["learned"]["qps"] / res["plain"]["qps"], 3)
     ix.close()
+    # recall@10 against exact brute force over every evaluation query (the
+    # three forms return identical results)
+    from oracle import oracle as O
+
+    ora = O.Index(w.docs, w.n, w.m, w.h, w.hash_seed)
+    rec = round(recall_vs_exact(ora, eq, ref[0].astype(np.int64), ref[2], 10, O.max_threads()), 4)
+    for name in ("plain", "batched", "learned"):
+        res[name]["recall_at_10"] = rec
+    log("small recall@10 %.4f (%d queries)" % (rec, nq))
     return res
 
 

@@ -112,6 +112,31 @@ snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t *ids, cons
 snn_status snn_delete(snn_index *ix, uint32_t id);
 snn_status snn_delete_batch(snn_index *ix, uint32_t n, const uint32_t *ids);
 
+/* Compaction of the inverted lists (Section 4.1, Notes on Implementation:
+ * the paper holds each list as a compressed list that is a bitmap where dense
+ * and an array of offsets where sparse). Every coordinate keeps its posting
+ * bitmap, which inserts and deletes update; this call gives each coordinate
+ * whose postings cover at most 1/16 of the used slots an array container too
+ * (per block of 1,024 slots, the offsets of its postings), so that scoring it
+ * costs work per posting rather than per slot. Searches are correct with or
+ * without it; blocks changed after it are read from the bitmaps until the next
+ * compaction, with identical results. It waits for all work on the device,
+ * reads every bitmap once and replaces the containers; it may be called any
+ * time the index is not used by another thread (not during snn_serve_run).
+ * classes (nullable, host, dim bytes): pin the coordinates that get arrays
+ * (non-zero = array) instead of choosing by density. Which coordinates hold
+ * arrays decides how a score's terms are grouped (the array terms are summed
+ * apart, then added), so it changes the last bits of scores (within the FP32
+ * tolerance); two indexes with equal live documents and equal classes give
+ * identical results. A coordinate whose array table would exceed 4 GiB of
+ * block offsets, or 2^32 postings in all, keeps its bitmap only.
+ * Errors: SNN_E_NOMEM, SNN_E_DEVICE (the index is unchanged). */
+snn_status snn_compact(snn_index *ix, const uint8_t *classes);
+
+/* The container class of every coordinate after the last snn_compact (dim
+ * bytes: 1 = array container, 0 = bitmap only; all 0 before any compaction). */
+snn_status snn_container_classes(snn_index *ix, uint8_t *out);
+
 /* Search one query (Alg. 6 scoring with T = infinity, then Alg. 3 / Alg. 7 with
  * k' = k). Writes up to k results to out_ids / out_scores (caller-allocated, k
  * entries each) and the result count to *out_count. Host pointers; returns
@@ -164,7 +189,7 @@ snn_status snn_search_batch_dev(snn_index *ix, uint32_t nq, const uint64_t *indp
  * The device current at the call must be the one current at snn_create.
  * Errors: SNN_E_INVALID (as snn_search_batch_dev; SNN_MODE_LEARNED; another
  * device current; a batch whose workspace exceeds the array: about
- * nq x tiles x min(k, tile) x 8 bytes of tile candidates plus 12 bytes per
+ * nq x tiles x min(k, tile) x 8 bytes of tile candidates plus 16 bytes per
  * query entry and a few words per query, with tiles = ceil(slots used / tile)
  * and a tile of 256 R slots, R from the schedule), SNN_E_DEVICE. */
 #define SNN_NOALLOC_SCRATCH_BYTES (64ull << 20)

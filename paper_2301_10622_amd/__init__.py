@@ -39,7 +39,7 @@ EXPORTS = [
     "snn_profile_read_updates", "snn_autotune", "snn_get_schedule", "snn_set_schedule",
     "snn_filter_train", "snn_filter_features", "snn_filter_predict", "snn_filter_get_params",
     "snn_filter_set_params", "snn_filter_set_delta", "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run",
-    "snn_search_batch_dev_noalloc",
+    "snn_search_batch_dev_noalloc", "snn_compact", "snn_container_classes",
 ]
 NOALLOC_SCRATCH_BYTES = 64 << 20
 MLP_PARAMS = 49537
@@ -138,6 +138,8 @@ def lib():
         L.snn_search_batch.argtypes = [P, u32, P, P, P, u32, P, P, P]
         L.snn_search_batch_dev.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
         L.snn_search_batch_dev_noalloc.argtypes = [P, u32, P, u64, P, P, u32, u32, P, P, P, P]
+        L.snn_compact.argtypes = [P, P]
+        L.snn_container_classes.argtypes = [P, P]
         L.snn_last_batch_status.argtypes = [P, P, P]
         L.snn_search_rerank.argtypes = [P, u32, P, P, P, u32, u32, P, P, P]
         L.snn_search_ex.argtypes = [P, u32, P, P, P, u32, P, P, P, P]
@@ -172,7 +174,8 @@ def lib():
                      "snn_read_sketch", "snn_profile_enable", "snn_profile_read", "snn_profile_read_updates", "snn_autotune",
                      "snn_get_schedule", "snn_set_schedule", "snn_filter_train", "snn_filter_features",
                      "snn_filter_predict", "snn_filter_get_params", "snn_filter_set_params", "snn_filter_set_delta",
-                     "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run", "snn_search_batch_dev_noalloc"):
+                     "snn_filter_enable", "snn_mlp_loss_grad", "snn_serve_run", "snn_search_batch_dev_noalloc", "snn_compact",
+                     "snn_container_classes"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -226,6 +229,21 @@ class Index:
     def _check(self, st: int):
         if st != SNN_OK:
             raise SnnError(st, lib().snn_last_error(self._h).decode())
+
+    def compact(self, classes=None):
+        """snn_compact: array containers for the sparse coordinates (or the
+        pinned `classes`, dim bytes, non-zero = array)."""
+        if classes is None:
+            self._check(lib().snn_compact(self._h, None))
+        else:
+            c = np.ascontiguousarray(classes, dtype=np.uint8)
+            assert c.shape == (self.dim,)
+            self._check(lib().snn_compact(self._h, _p(c)))
+
+    def container_classes(self) -> np.ndarray:
+        out = np.zeros(self.dim, np.uint8)
+        self._check(lib().snn_container_classes(self._h, _p(out)))
+        return out
 
     # ------------------------------------------------------------------ updates
     def insert(self, id: int, coords, vals):
@@ -525,8 +543,9 @@ class Index:
         return u, l
 
 
-def load_docs(index: Index, docs, ids: Optional[np.ndarray] = None, chunk: int = 1 << 18):
-    """Insert a CSR batch of documents (ids default to 0..rows-1)."""
+def load_docs(index: Index, docs, ids: Optional[np.ndarray] = None, chunk: int = 1 << 18, compact=True):
+    """Insert a CSR batch of documents (ids default to 0..rows-1), then compact
+    the lists (compact: True, False, or the pinned classes)."""
     n = docs.rows
     if ids is None:
         ids = np.arange(n, dtype=np.uint32)
@@ -536,3 +555,7 @@ def load_docs(index: Index, docs, ids: Optional[np.ndarray] = None, chunk: int =
         c = docs.coords[docs.indptr[a]:docs.indptr[b]]
         v = docs.vals[docs.indptr[a]:docs.indptr[b]]
         index.insert_batch(ids[a:b], ip, c, v)
+    if compact is True:
+        index.compact()
+    elif compact is not False and compact is not None:
+        index.compact(classes=compact)

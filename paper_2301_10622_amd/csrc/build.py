@@ -8,7 +8,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libsnn.so")
 SOURCES = ["kernels_index.hip", "kernels_search.hip", "kernels_merge.hip", "kernels_mlp.hip", "kernels_rerank.hip", "snn_api.cpp",
-           "snn_extras.cpp", "snn_tune.cpp", "snn_filter.cpp", "snn_serve.cpp", "snn_noalloc.cpp"]
+           "snn_extras.cpp", "snn_tune.cpp", "snn_filter.cpp", "snn_serve.cpp", "snn_noalloc.cpp", "snn_lists.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

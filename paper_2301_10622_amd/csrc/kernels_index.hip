@@ -23,6 +23,8 @@ namespace snn {
 //   4. with a forward store, the document's (coordinate, value) pairs are
 //      copied to its region (doc_off, placed by the host).
 // The caller guarantees the slot's old postings were cleared before (delete).
+// The slot's block is marked stale: until the next compaction, searches read
+// its postings from the bitmaps.
 // ---------------------------------------------------------------------------
 
 // Document of workgroup b in an update launch over n documents (8 * ceil(n / 8)
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
   if (lane == 0) {
     ix.slot2id[slot] = ids[d];
     atomicOr((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)(1ull << slot_bit(slot)));
+    ix.stale[slot >> 10] = 1u;  // the block's array containers no longer list all its postings
   }
 }
 
@@ -132,9 +135,11 @@ __global__ __launch_bounds__(64) void k_delete(DevIndex ix, uint32_t n, const ui
   const uint32_t slot = slots[d];
   const uint64_t pmask = ~(1ull << post_bit(slot));
   const size_t pword = post_word(slot);
-  if (clear_bits)
+  if (clear_bits) {
     for (uint64_t e = indptr[d] + threadIdx.x; e < indptr[d + 1]; e += 64)
       atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + pword], (unsigned long long)pmask);
+    if (threadIdx.x == 0) ix.stale[slot >> 10] = 1u;  // its array containers still list the slot
+  }
   if (clear_live && threadIdx.x == 0)
     atomicAnd((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)~(1ull << slot_bit(slot)));
 }
@@ -145,6 +150,116 @@ hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, 
   if (n > kUpdMaxDocs) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_delete, dim3(upd_grid(n)), dim3(64), 0, s, ix, n, slots, indptr, coords, clear_bits,
                      clear_live);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Compaction: array containers (Section 4.1, Notes on Implementation: the
+// lists are held as Roaring holds them, an array of offsets where a block is
+// sparse). k_count_rows counts each coordinate's postings; the host picks the
+// coordinates that get an array container and their place in `post`;
+// k_build_lists then writes, per such coordinate and 1,024-slot block, the
+// segment start and the block offsets of the set bits.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_count_rows(DevIndex ix, uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t red[4];
+  const uint32_t j = blockIdx.x;
+  const uint64_t *row = ix.bits + (size_t)j * ix.W;
+  uint32_t c = 0;
+  for (uint32_t w = threadIdx.x; w < ix.W; w += blockDim.x) c += (uint32_t)__popcll(row[w]);
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) cnt[j] = red[0] + red[1] + red[2] + red[3];
+}
+
+hipError_t launch_count_rows(const DevIndex &ix, uint32_t *cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_rows, dim3(ix.dim), dim3(256), 0, s, ix, cnt);
+  return hipGetLastError();
+}
+
+constexpr uint32_t kListChunk = 2048;  // blocks per pass of k_build_lists (8 per thread)
+
+// One workgroup per array row r (coordinate row_coord[r]): segment starts
+// seg[r][b] = rbase[r] + postings of the row in blocks before b, and
+// seg[r][nblk] = rbase[r] + the row's count; the postings of block b go to
+// post[seg[r][b] ..] as block offsets, lane l's set bits in bit order.
+__global__ __launch_bounds__(256) void k_build_lists(DevIndex ix, const uint32_t *__restrict__ row_coord,
+                                                     const uint64_t *__restrict__ rbase, uint32_t *__restrict__ seg,
+                                                     uint16_t *__restrict__ post) {
+  __shared__ uint32_t cb[kListChunk];
+  __shared__ uint32_t wsum[4];
+  const uint32_t r = blockIdx.x;
+  const uint32_t j = row_coord[r];
+  const uint32_t nblk = ix.cap >> 10;
+  const uint64_t *row = ix.bits + (size_t)j * ix.W;
+  uint32_t *sr = seg + (size_t)r * (nblk + 1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t carry = rbase[r];
+  for (uint32_t b0 = 0; b0 < nblk; b0 += kListChunk) {
+    const uint32_t nb = min(kListChunk, nblk - b0);
+    // postings per block, 8 consecutive blocks per thread
+    uint32_t loc[8], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t i = threadIdx.x * 8u + (uint32_t)k;
+      uint32_t c = 0;
+      if (i < nb) {
+        const uint64_t *w = row + (size_t)(b0 + i) * 16u;
+#pragma unroll
+        for (int x = 0; x < 16; ++x) c += (uint32_t)__popcll(w[x]);
+      }
+      loc[k] = c;
+      tot += c;
+    }
+    // exclusive scan of the per-thread totals: in the wave, then over the waves
+    uint32_t inc = tot;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    uint32_t ex = inc - tot;
+    for (int w = 0; w < wave; ++w) ex += wsum[w];
+    const uint32_t chunk_total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t i = threadIdx.x * 8u + (uint32_t)k;
+      if (i < nb) {
+        cb[i] = ex;
+        sr[b0 + i] = (uint32_t)(carry + ex);
+      }
+      ex += loc[k];
+    }
+    __syncthreads();
+    // offsets: a wave per block, each lane its 16-bit chunk of the block
+    for (uint32_t i = (uint32_t)wave; i < nb; i += 4u) {
+      const uint32_t bits = ((const uint16_t *)(row + (size_t)(b0 + i) * 16u))[lane];
+      const uint32_t c = (uint32_t)__popc(bits);
+      uint32_t pinc = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(pinc, o);
+        if (lane >= o) pinc += y;
+      }
+      uint64_t at = carry + cb[i] + (pinc - c);
+      uint32_t b = bits;
+      while (b) {
+        const uint32_t x = (uint32_t)__builtin_ctz(b);
+        b &= b - 1u;
+        post[at++] = (uint16_t)(256u * (x >> 2) + 4u * (uint32_t)lane + (x & 3u));
+      }
+    }
+    carry += chunk_total;
+    __syncthreads();  // cb and wsum are reused by the next chunk
+  }
+  if (threadIdx.x == 0) sr[nblk] = (uint32_t)carry;
+}
+
+hipError_t launch_build_lists(const DevIndex &ix, uint32_t nrows, const uint32_t *row_coord, const uint64_t *rbase,
+                              uint32_t *seg, uint16_t *post, hipStream_t s) {
+  if (nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_lists, dim3(nrows), dim3(256), 0, s, ix, row_coord, rbase, seg, post);
   return hipGetLastError();
 }
 
@@ -251,23 +366,39 @@ __device__ inline void bitonic_sort_u64_asc(uint64_t *s, int n) {
   __syncthreads();
 }
 
+// Scoring order of the scored entries (the first min(nz, max_coords) in the
+// Alg. 6 order): those of coordinates with a bitmap container only come first
+// -- with h = 1 by sketch row, ties in the Alg. 6 order; with h > 1 in the
+// Alg. 6 order -- then those with an array container (crow[j] != kNoRow), in
+// the Alg. 6 order; the entries past the budget follow. nd[q] counts the first
+// kind; cr[e] holds the array row of each entry of the second.
+__device__ __forceinline__ uint32_t prep_row(const DevIndex &ix, const uint32_t *crow, uint32_t j, uint32_t sign,
+                                             bool scored) {
+  if (!scored) return 0x7FFFFFFFu;
+  if (crow && crow[j] != kNoRow) return 0x7FFFFFFEu;
+  return ix.h == 1 ? (ix.bucket[j] << 1) | sign : 0u;
+}
+
 __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const uint32_t *__restrict__ coords,
                                               const float *__restrict__ vals, uint32_t max_coords,
-                                              uint32_t *__restrict__ nz_full) {
+                                              uint32_t *__restrict__ nz_full, const uint32_t *__restrict__ crow) {
   __shared__ uint64_t keys[kPrepCap];
   __shared__ uint32_t bad;
   __shared__ uint32_t nz;
+  __shared__ uint32_t ndense;
   const uint32_t q = blockIdx.x;
   const uint64_t e0 = qd.qptr[q];
   const uint64_t len64 = qd.qptr[q + 1] - e0;
   if (threadIdx.x == 0) {
     bad = len64 > (uint64_t)kPrepCap ? 1u : 0u;
     nz = 0;
+    ndense = 0;
   }
   __syncthreads();
   if (bad) {
     if (threadIdx.x == 0) {
       qd.cnt[q] = 0;
+      qd.nd[q] = 0;
       qd.status[q] = 1;
       if (nz_full) nz_full[q] = 0;
     }
@@ -304,12 +435,14 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       }
     }
     __syncthreads();  // `bad` and `nz` are final
-    // scoring order: with h = 1 the scored entries by (row, rank), the rest after in rank order
+    // scoring order (prep_row), by (row, rank)
     const uint32_t scored = min(nz, max_coords);
     uint64_t ok = ~0ull;
+    uint32_t row = 0x7FFFFFFFu;
     if (t < len && !bad && key != ~0ull) {
-      const uint32_t row = ix.h == 1 && rank < scored ? (ix.bucket[j] << 1) | (vb >> 31) : 0x7FFFFFFFu;
+      row = prep_row(ix, crow, j, vb >> 31, rank < scored);
       ok = ((uint64_t)row << 32) | rank;
+      if (row < 0x7FFFFFFEu) atomicAdd(&ndense, 1u);
     }
     if (t < len) okey[t] = ok;
     __syncthreads();
@@ -322,9 +455,11 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
       if (ix.h == 1) qd.b[e] = (ix.bucket[j] << 1) | (vb >> 31);  // the sketch row: bucket, then U / L
       else
         for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+      if (row == 0x7FFFFFFEu) qd.cr[e] = crow[j];
     }
     if (t == 0) {
       qd.cnt[q] = bad ? 0u : min(nz, max_coords);
+      qd.nd[q] = bad ? 0u : ndense;
       qd.status[q] = bad ? 1u : 0u;
       if (nz_full) nz_full[q] = bad ? 0u : nz;
     }
@@ -359,6 +494,7 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
   if (bad) {
     if (threadIdx.x == 0) {
       qd.cnt[q] = 0;
+      qd.nd[q] = 0;
       qd.status[q] = 1;
       if (nz_full) nz_full[q] = 0;
     }
@@ -376,21 +512,23 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
   }
   bitonic_sort_u64_asc(keys, n);
   const uint32_t cnt = nz;
-  // scoring order (see above): sort (row, rank) of the scored entries, h = 1
+  // scoring order (prep_row): sort (row, rank)
   __shared__ uint64_t okeys[kPrepCap];
   const uint32_t scored = min(cnt, max_coords);
   for (uint32_t i = threadIdx.x; i < (uint32_t)n; i += blockDim.x) {
     uint64_t ok = ~0ull;
     if (i < cnt) {
       const uint32_t lo = (uint32_t)keys[i];
-      const uint32_t row = ix.h == 1 && i < scored ? (ix.bucket[lo >> 1] << 1) | (lo & 1u) : 0x7FFFFFFFu;
+      const uint32_t row = prep_row(ix, crow, lo >> 1, lo & 1u, i < scored);
       ok = ((uint64_t)row << 32) | i;
+      if (row < 0x7FFFFFFEu) atomicAdd(&ndense, 1u);
     }
     okeys[i] = ok;
   }
   bitonic_sort_u64_asc(okeys, n);
   for (uint32_t p = threadIdx.x; p < cnt; p += blockDim.x) {
-    const uint64_t k = keys[(uint32_t)okeys[p]];
+    const uint64_t ok = okeys[p];
+    const uint64_t k = keys[(uint32_t)ok];
     const uint32_t ab = ~(uint32_t)(k >> 32);
     const uint32_t lo = (uint32_t)k;
     const uint32_t j = lo >> 1;
@@ -401,19 +539,21 @@ __global__ __launch_bounds__(256) void k_prep(DevIndex ix, QueryDesc qd, const u
     if (ix.h == 1) qd.b[e] = (ix.bucket[j] << 1) | (vb >> 31);  // the sketch row: bucket, then U / L
     else
       for (uint32_t o = 0; o < ix.h; ++o) qd.b[e * ix.h + o] = ix.bucket[(size_t)o * ix.dim + j];
+    if ((uint32_t)(ok >> 32) == 0x7FFFFFFEu) qd.cr[e] = crow[j];
   }
   if (threadIdx.x == 0) {
     qd.cnt[q] = min(cnt, max_coords);
+    qd.nd[q] = ndense;
     qd.status[q] = 0;
     if (nz_full) nz_full[q] = cnt;
   }
 }
 
 hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
-                       uint32_t max_coords, uint32_t *nz_full, hipStream_t s) {
+                       uint32_t max_coords, uint32_t *nz_full, const uint32_t *crow, hipStream_t s) {
   if (nq == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3(nq), dim3(256), 0, s, ix, qd, coords, vals, max_coords ? max_coords : 0xFFFFFFFFu,
-                     nz_full);
+                     nz_full, crow);
   return hipGetLastError();
 }
 

@@ -194,8 +194,148 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t wslot0, int x, int lane) {
 template <int R>
 __device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&acc)[R], SelShared &sh);
 
+// ---------------- entries with array containers ----------------
+// A query's entries past nd[q] belong to coordinates whose postings are also
+// held as per-block offset lists (array containers). For each such entry and
+// each 1,024-slot block of the wave, the wave reads the block's segment -- at
+// most 64 offsets per step, one per lane -- gathers each listed slot's bound
+// and adds q_j * bound into that slot's score in LDS: work per posting, not
+// per slot. The entries go in the Alg. 6 order; within one entry the listed
+// slots are distinct, so no two lanes touch one score, and the wave's LDS
+// operations complete in issue order. In a block changed since the last
+// compaction (stale) the same entries are read from the posting bitmaps and
+// the same terms added in the same order, so both give identical bits. The
+// LDS sums are added to the register scores at the end, one add per slot.
+
+// One bound of a slot: q > 0 reads min_o U[pi_o(j)][slot], q < 0 max_o L[...].
+// kH1: h = 1, where the prepared row (bucket << 1 | q < 0) names the half.
+template <bool kBf16, bool kH1>
+__device__ __forceinline__ float gather_bound(const DevIndex &ix, cptr<uint32_t> qb, uint64_t e, uint32_t h,
+                                              bool upper, uint32_t slot) {
+  auto one = [&](uint32_t row, bool up) -> float {
+    const size_t at = (size_t)row * ix.cap + slot;
+    if constexpr (kBf16) {
+      const uint16_t x = ((const uint16_t *)(up ? ix.U : ix.L))[at];
+      return __builtin_bit_cast(float, (uint32_t)x << 16);
+    } else {
+      return (up ? ix.U : ix.L)[at];
+    }
+  };
+  if (kH1 || h == 1) {
+    const uint32_t b = qb[e];  // (bucket << 1) | (q < 0)
+    return one(b >> 1, (b & 1u) == 0u);
+  }
+  float v = one(qb[e * h], upper);
+  for (uint32_t o = 1; o < h; ++o) {
+    const float x = one(qb[e * h + o], upper);
+    v = upper ? __builtin_fminf(v, x) : __builtin_fmaxf(v, x);
+  }
+  return v;
+}
+
+// sp: the wave's 256 G scores in LDS (slot wslot0 + x at sp[x]); sets them to
+// the sums of the terms of entries [e_begin, e_end).
+template <int R, bool kBf16, int SC, bool kH1>
+__device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end, uint32_t wslot0, float *sp) {
+  constexpr int G = R / 4;
+  constexpr uint32_t kSpan = 256u * G;  // slots of the wave
+  const int lane = threadIdx.x & 63;
+  const DevIndex &ix = a.ix;
+  const cptr<uint32_t> qj = as_const(a.qd.j);
+  const cptr<float> qq = as_const(a.qd.q);
+  const cptr<uint32_t> qb = as_const(a.qd.b);
+  const cptr<uint32_t> qc = as_const(a.qd.cr);
+  const cptr<uint32_t> sg = as_const(ix.seg);
+  const uint32_t h = ix.h;
+  const uint32_t nblk1 = (ix.cap >> 10) + 1u;
+#pragma unroll
+  for (int r = 0; r < G; ++r) *(float4 *)(sp + 256 * r + 4 * lane) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  __builtin_amdgcn_wave_barrier();
+  // blocks of the wave: G / 4 whole blocks, or (G = 2) half of one
+  constexpr uint32_t nb = G >= 4 ? (uint32_t)(G / 4) : 1u;
+  for (uint32_t bi = 0; bi < nb; ++bi) {
+    const uint32_t blk = (wslot0 >> 10) + bi;
+    const uint32_t bslot0 = blk << 10;                           // first slot of the block
+    const uint32_t lo = wslot0 > bslot0 ? wslot0 - bslot0 : 0u;  // the wave's part of the block
+    const uint32_t hi = min(lo + kSpan, 1024u);
+    float *spb = sp + (bslot0 + lo - wslot0);  // spb[o - lo]: block offset o, for lo <= o < hi
+    // one term: the bound of the slot at block offset o, into its score
+    auto add = [&](uint64_t e, float q, uint32_t o) {
+      if (o >= lo && o < hi) {
+        const float v = gather_bound<kBf16, kH1>(ix, qb, e, h, q > 0.0f, bslot0 + o);
+        spb[o - lo] = __builtin_fmaf(q, v, spb[o - lo]);
+      }
+    };
+    if (as_const(ix.stale)[blk] == 0u) {
+      for (uint64_t e = e_begin; e < e_end; e += SC) {
+        // the chunk's segments, offsets and bounds are all requested before
+        // the first add; the adds then go entry by entry
+        uint32_t s0[SC], n[SC], off[SC];
+        float qv[SC], v[SC];
+#pragma unroll
+        for (int k = 0; k < SC; ++k) {
+          const bool in = e + k < e_end;
+          const uint64_t ek = in ? e + k : e;
+          const size_t rb = (size_t)qc[ek] * nblk1 + blk;
+          s0[k] = sg[rb];
+          n[k] = in ? sg[rb + 1] - s0[k] : 0u;
+          qv[k] = qq[ek];
+        }
+#pragma unroll
+        for (int k = 0; k < SC; ++k) {
+          off[k] = (uint32_t)lane < n[k] ? (uint32_t)ix.post[s0[k] + lane] : 0xFFFFu;
+          const bool mine = off[k] >= lo && off[k] < hi;
+          v[k] = mine ? gather_bound<kBf16, kH1>(ix, qb, e + k, h, qv[k] > 0.0f, bslot0 + off[k]) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < SC; ++k) {
+          if (off[k] >= lo && off[k] < hi) spb[off[k] - lo] = __builtin_fmaf(qv[k], v[k], spb[off[k] - lo]);
+          __builtin_amdgcn_wave_barrier();
+          // the rest of a segment longer than one wave step (rare: the class
+          // is chosen for at most 64 postings per block on average), before
+          // the next entry's adds
+          for (uint32_t p0 = 64; p0 < n[k]; p0 += 64) {
+            const uint32_t o = p0 + (uint32_t)lane < n[k] ? (uint32_t)ix.post[s0[k] + p0 + lane] : 0xFFFFu;
+            add(e + k, qv[k], o);
+            __builtin_amdgcn_wave_barrier();
+          }
+        }
+      }
+    } else {
+      // stale block: the same terms from the posting bitmaps; lane l owns
+      // block offsets 256g + 4l + i, at bit 4g + i of its 16-bit chunk
+      for (uint64_t e = e_begin; e < e_end; ++e) {
+        const uint32_t j = qj[e];
+        const float q = qq[e];
+        uint32_t bits = (uint32_t)((const uint16_t *)(ix.bits + (size_t)j * ix.W + ((size_t)blk << 4)))[lane];
+        while (bits) {
+          const uint32_t x = (uint32_t)__builtin_ctz(bits);
+          bits &= bits - 1u;
+          add(e, q, 256u * (x >> 2) + 4u * (uint32_t)lane + (x & 3u));
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// acc += the wave's LDS sums (one add per slot)
+template <int R>
+__device__ __forceinline__ void fold_arrays(const float *sp, float (&acc)[R]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < R / 4; ++r) {
+    const float4 x = *(const float4 *)(sp + 256 * r + 4 * lane);
+    acc[4 * r + 0] += x.x;
+    acc[4 * r + 1] += x.y;
+    acc[4 * r + 2] += x.z;
+    acc[4 * r + 3] += x.w;
+  }
+}
+
 template <int R, bool kBf16>
-__device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
+__device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh, float *sp) {
   constexpr int G = R / 4;  // 256-slot groups per wave
   using LB = typename LaneBits<G>::type;
   const int lane = threadIdx.x & 63;
@@ -219,6 +359,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
 
   const uint64_t e0 = as_const(a.qd.qptr)[q] - a.qd.ebase;
   const uint32_t ne = as_const(a.qd.cnt)[q];
+  const uint32_t nd = as_const(a.qd.nd)[q];  // entries scored from bitmaps; the rest from arrays
   const uint32_t h = ix.h;
   const cptr<uint32_t> qj = as_const(a.qd.j);
   const cptr<float> qq = as_const(a.qd.q);
@@ -279,13 +420,13 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
   // load per lane and 1,024-slot block each), so their memory latency is paid
   // once per chunk rather than once per coordinate.
   LB cb[kChunk];
-  for (uint32_t c = 0; c < ne;) {
+  for (uint32_t c = 0; c < nd;) {
     if (c % kChunk == 0) {
 #pragma unroll
-      for (int k = 0; k < kChunk; ++k) cb[k] = lane_bits<G>(ix, qj[e0 + min(c + (uint32_t)k, ne - 1u)], wslot0, lane);
+      for (int k = 0; k < kChunk; ++k) cb[k] = lane_bits<G>(ix, qj[e0 + min(c + (uint32_t)k, nd - 1u)], wslot0, lane);
     }
     if (h == 1) {
-      const bool two = c + 1u < ne;
+      const bool two = c + 1u < nd;
       score_two(c, cb[0], two ? c + 1u : c, two ? cb[1] : (LB)0);
       c += 2;
 #pragma unroll
@@ -296,6 +437,10 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
 #pragma unroll
       for (int k = 0; k + 1 < kChunk; ++k) cb[k] = cb[k + 1];
     }
+  }
+  if (nd < ne) {
+    score_arrays<R, kBf16, (R <= 16 ? 4 : 64 / R), false>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
+    fold_arrays<R>(sp + wave * 64 * R, acc);
   }
 
   finish<R>(a, q, t, acc, sh);
@@ -414,7 +559,7 @@ __device__ void finish(const TileArgs &a, uint32_t q, uint32_t t, const float (&
 // query alone uses. Scores of the Q queries stay in registers; each then goes
 // through the same selection as a single query.
 template <int R, bool kBf16, int Q>
-__device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t nq_eff, SelShared &sh) {
+__device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t nq_eff, SelShared &sh, float *sp) {
   constexpr int G = R / 4;
   static_assert(G <= 4, "grouped tiles cover at most one 1,024-slot block per wave");
   const int lane = threadIdx.x & 63;
@@ -429,7 +574,7 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
   // positions: the host keeps a grouped batch below 2^32 entries), the sketch
   // row of the entry under the cursor (none past the end) and the posting bits
   // of the next entries, fetched kChunk at a time (cb[i][0] is the cursor's)
-  uint32_t qid[Q], row[Q], left[Q], cur[Q], end[Q];
+  uint32_t qid[Q], row[Q], left[Q], cur[Q], end[Q], aend[Q];
   uint32_t cb[Q][kChunk];
   auto refill = [&](int i) {
     // the chunk's coordinates in one scalar load (the entry array is padded by
@@ -447,14 +592,15 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
   for (int i = 0; i < Q; ++i) {
     const uint32_t slot = grp * (uint32_t)Q + (uint32_t)i;
     qid[i] = kNone;
-    cur[i] = end[i] = 0;
+    cur[i] = end[i] = aend[i] = 0;
     left[i] = 0;
     if (slot < nq_eff) {
       const uint32_t q = a.qlist ? as_const(a.qlist)[slot] : slot;
       qid[i] = q;
       if (as_const(a.qd.status)[q] == 0u) {
         cur[i] = (uint32_t)(as_const(a.qd.qptr)[q] - a.qd.ebase);
-        end[i] = cur[i] + as_const(a.qd.cnt)[q];
+        end[i] = cur[i] + as_const(a.qd.nd)[q];     // bitmap entries, walked by row below
+        aend[i] = cur[i] + as_const(a.qd.cnt)[q];   // array entries [end, aend) after them
       }
     }
     row[i] = kNone;
@@ -515,6 +661,24 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
       }
     }
   }
+  // each query's array entries (the cursor stopped at its bitmap entries'
+  // end), one query at a time through the wave's LDS scores
+#pragma unroll 1
+  for (int i = 0; i < Q; ++i) {
+    uint32_t b = cur[0], en = aend[0];
+#pragma unroll
+    for (int ii = 1; ii < Q; ++ii)
+      if (ii == i) {
+        b = cur[ii];
+        en = aend[ii];
+      }
+    if (b < en) {
+      score_arrays<R, kBf16, 4, true>(a, b, en, wslot0, sp + wave * 64 * R);
+#pragma unroll
+      for (int ii = 0; ii < Q; ++ii)
+        if (ii == i) fold_arrays<R>(sp + wave * 64 * R, acc[ii]);
+    }
+  }
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (qid[i] == kNone) continue;
@@ -533,7 +697,7 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
 // of the next chunk, and then applied in entry order (the same terms, added in
 // the same order as tile_body). h = 1 only; registers are plentiful here.
 template <int R, bool kBf16>
-__device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh) {
+__device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, SelShared &sh, float *sp) {
   constexpr int G = R / 4;
   constexpr int PC = 4;  // entries per chunk
   using LB = typename LaneBits<G>::type;
@@ -550,24 +714,25 @@ __device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, Sel
   for (int x = 0; x < R; ++x) acc[x] = 0.0f;
   const uint64_t e0 = as_const(a.qd.qptr)[q] - a.qd.ebase;
   const uint32_t ne = as_const(a.qd.cnt)[q];
+  const uint32_t nd = as_const(a.qd.nd)[q];  // entries scored from bitmaps; the rest from arrays
   const cptr<uint32_t> qj = as_const(a.qd.j);
   const cptr<float> qq = as_const(a.qd.q);
   const cptr<uint32_t> qb = as_const(a.qd.b);
   LB cb[PC];
 #pragma unroll
-  for (int k = 0; k < PC; ++k) cb[k] = ne ? lane_bits<G>(ix, qj[e0 + min((uint32_t)k, ne - 1u)], wslot0, lane) : (LB)0;
-  for (uint32_t c0 = 0; c0 < ne; c0 += PC) {
+  for (int k = 0; k < PC; ++k) cb[k] = nd ? lane_bits<G>(ix, qj[e0 + min((uint32_t)k, nd - 1u)], wslot0, lane) : (LB)0;
+  for (uint32_t c0 = 0; c0 < nd; c0 += PC) {
     LB nb[PC];
-    const bool more = c0 + PC < ne;
+    const bool more = c0 + PC < nd;
 #pragma unroll
     for (int k = 0; k < PC; ++k)
-      nb[k] = more ? lane_bits<G>(ix, qj[e0 + min(c0 + PC + (uint32_t)k, ne - 1u)], wslot0, lane) : (LB)0;
+      nb[k] = more ? lane_bits<G>(ix, qj[e0 + min(c0 + PC + (uint32_t)k, nd - 1u)], wslot0, lane) : (LB)0;
     float v[PC][G][4];
     uint32_t qbits[PC];
 #pragma unroll
     for (int k = 0; k < PC; ++k) {
-      const uint32_t c = min(c0 + (uint32_t)k, ne - 1u);  // past the end: a repeat with no bits
-      const LB bk = c0 + (uint32_t)k < ne ? cb[k] : (LB)0;
+      const uint32_t c = min(c0 + (uint32_t)k, nd - 1u);  // past the end: a repeat with no bits
+      const LB bk = c0 + (uint32_t)k < nd ? cb[k] : (LB)0;
       cb[k] = bk;
       const float qv = qq[e0 + c];
       qbits[k] = __builtin_bit_cast(uint32_t, qv);
@@ -589,29 +754,35 @@ __device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, Sel
 #pragma unroll
     for (int k = 0; k < PC; ++k) cb[k] = nb[k];
   }
+  if (nd < ne) {
+    score_arrays<R, kBf16, (R <= 16 ? 8 : 64 / R), true>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
+    fold_arrays<R>(sp + wave * 64 * R, acc);
+  }
   finish<R>(a, q, t, acc, sh);
 }
 
 template <int R, bool kBf16>
-__device__ __forceinline__ void one_item(const TileArgs &a, SelShared &sh) {
+__device__ __forceinline__ void one_item(const TileArgs &a, SelShared &sh, float *sp) {
   uint32_t q = a.q0 + blockIdx.y;
   if (a.qlist) {
     if (q >= *as_const(a.nlist)) return;
     q = as_const(a.qlist)[q];
   }
-  tile_body<R, kBf16>(a, q, blockIdx.x, sh);
+  tile_body<R, kBf16>(a, q, blockIdx.x, sh, sp);
 }
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles(TileArgs a) {
   __shared__ SelShared sh;
-  one_item<R, false>(a, sh);
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
+  one_item<R, false>(a, sh, sp);
 }
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles_bf16(TileArgs a) {
   __shared__ SelShared sh;
-  one_item<R, true>(a, sh);
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
+  one_item<R, true>(a, sh, sp);
 }
 
 // the plain form: query a.q0 alone, one workgroup per tile (R = 64 keeps the
@@ -619,8 +790,9 @@ __global__ __launch_bounds__(kBlock) void k_tiles_bf16(TileArgs a) {
 template <int R, bool kBf16>
 __global__ __launch_bounds__(kBlock) void k_tiles_latency(TileArgs a) {
   __shared__ SelShared sh;
-  if (R <= 32 && a.ix.h == 1) tile_body_latency<R, kBf16>(a, a.q0, blockIdx.x, sh);
-  else tile_body<R, kBf16>(a, a.q0, blockIdx.x, sh);
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
+  if (R <= 32 && a.ix.h == 1) tile_body_latency<R, kBf16>(a, a.q0, blockIdx.x, sh, sp);
+  else tile_body<R, kBf16>(a, a.q0, blockIdx.x, sh, sp);
 }
 
 // Persistent form: a fixed grid pulls (query, tile) items from per-XCD queues.
@@ -630,7 +802,7 @@ __global__ __launch_bounds__(kBlock) void k_tiles_latency(TileArgs a) {
 // for many queries while those slices sit in that XCD's L2. A drained queue
 // steals from the others; every workgroup exits once all queues are drained.
 template <int R, bool kBf16>
-__device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &sh) {
+__device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &sh, float *sp) {
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
@@ -647,7 +819,7 @@ __device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &s
       if (it >= items) break;
       const uint32_t t = x + X * (it / nq);
       const uint32_t q = a.qlist ? as_const(a.qlist)[it % nq] : it % nq;
-      tile_body<R, kBf16>(a, q, t, sh);
+      tile_body<R, kBf16>(a, q, t, sh, sp);
     }
   }
 }
@@ -655,13 +827,15 @@ __device__ __forceinline__ void persistent_items(const TileArgs &a, SelShared &s
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles_persistent(TileArgs a) {
   __shared__ SelShared sh;
-  persistent_items<R, false>(a, sh);
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
+  persistent_items<R, false>(a, sh, sp);
 }
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_tiles_persistent_bf16(TileArgs a) {
   __shared__ SelShared sh;
-  persistent_items<R, true>(a, sh);
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
+  persistent_items<R, true>(a, sh, sp);
 }
 
 // Grouped forms: items are (query group, tile); group g holds the queries
@@ -669,10 +843,11 @@ __global__ __launch_bounds__(kBlock) void k_tiles_persistent_bf16(TileArgs a) {
 template <int R, bool kBf16, int Q>
 __global__ __launch_bounds__(kBlock) void k_tiles_grouped(TileArgs a) {
   __shared__ SelShared sh;
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
   const uint32_t grp = a.q0 + blockIdx.y;
   if (grp * (uint32_t)Q >= nq) return;
-  tile_group<R, kBf16, Q>(a, grp, blockIdx.x, nq, sh);
+  tile_group<R, kBf16, Q>(a, grp, blockIdx.x, nq, sh, sp);
 }
 
 // Waves per SIMD the persistent grouped kernel is built for: with R = 16, two
@@ -688,6 +863,7 @@ template <int R, bool kBf16, int Q>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(GroupedWaves<R, kBf16, Q>::value)))
 void k_tiles_persistent_grouped(TileArgs a) {
   __shared__ SelShared sh;
+  __shared__ __align__(16) float sp[kWaves * 64 * R];
   const uint32_t X = a.xcds;
   const uint32_t home = blockIdx.x % X;
   const uint32_t nq = a.qlist ? *as_const(a.nlist) : a.nq;
@@ -703,7 +879,7 @@ void k_tiles_persistent_grouped(TileArgs a) {
       __syncthreads();
       const uint32_t it = sh.item;
       if (it >= items) break;
-      tile_group<R, kBf16, Q>(a, it % ng, x + X * (it / ng), nq, sh);
+      tile_group<R, kBf16, Q>(a, it % ng, x + X * (it / ng), nq, sh, sp);
     }
   }
 }

@@ -224,7 +224,8 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   if ((e = hipMalloc(&d.bits, bits_bytes)) != hipSuccess || (e = hipMalloc(&d.live, (size_t)ix->W * 8)) != hipSuccess ||
       (e = hipMalloc(&d.U, sk_bytes)) != hipSuccess || (lower && (e = hipMalloc(&d.L, sk_bytes)) != hipSuccess) ||
       (e = hipMalloc(&d.slot2id, (size_t)ix->cap * 4)) != hipSuccess ||
-      (e = hipMalloc(&d.bucket, (size_t)cfg->h * cfg->dim * 4)) != hipSuccess) {
+      (e = hipMalloc(&d.bucket, (size_t)cfg->h * cfg->dim * 4)) != hipSuccess ||
+      (e = hipMalloc(&d.stale, (size_t)(ix->cap >> 10) * 4)) != hipSuccess) {
     snn_status st = e == hipErrorOutOfMemory ? SNN_E_NOMEM : SNN_E_DEVICE;
     snn_destroy(ix);
     return st;
@@ -234,7 +235,8 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
       hipMemsetAsync(d.live, 0, (size_t)ix->W * 8, ix->stream) != hipSuccess ||
       hipMemsetAsync(d.U, 0, sk_bytes, ix->stream) != hipSuccess ||
       (lower && hipMemsetAsync(d.L, 0, sk_bytes, ix->stream) != hipSuccess) ||
-      launch_fill_u32(d.slot2id, 0xFFFFFFFFu, ix->cap, ix->stream) != hipSuccess) {
+      launch_fill_u32(d.slot2id, 0xFFFFFFFFu, ix->cap, ix->stream) != hipSuccess ||
+      launch_fill_u32(d.stale, 0u, ix->cap >> 10, ix->stream) != hipSuccess) {
     snn_destroy(ix);
     return SNN_E_DEVICE;
   }
@@ -283,6 +285,10 @@ extern "C" void snn_destroy(snn_index *ix) {
   if (d.L) (void)hipFree(d.L);
   if (d.slot2id) (void)hipFree(d.slot2id);
   if (d.bucket) (void)hipFree(d.bucket);
+  if (d.stale) (void)hipFree(d.stale);
+  ix->lists_seg.release();
+  ix->lists_post.release();
+  ix->crow.release();
   if (ix->fw.ent) (void)hipFree(ix->fw.ent);
   if (ix->fw.off) (void)hipFree(ix->fw.off);
   if (ix->fw.len) (void)hipFree(ix->fw.len);
@@ -591,6 +597,8 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   const size_t o_j = o; o += al((size_t)total * 4 + 64);  // the grouped kernel reads up to 16 entries past a list
   const size_t o_q = o; o += al((size_t)total * 4);
   const size_t o_b = o; o += al((size_t)total * 4 * h);
+  const size_t o_nd = o; o += al((size_t)nq * 4);
+  const size_t o_cr = o; o += al((size_t)total * 4);
   const size_t o_cc = o; o += al((size_t)nq * tiles * 4);
   const size_t o_queue = o; o += al(64 * 4);
   const size_t o_qlist = o; o += al((size_t)nq * 4);
@@ -639,6 +647,8 @@ snn_status snn_index::prepare_workspace(uint32_t nq, uint64_t total, uint32_t kt
   w.j = (uint32_t *)(p + o_j);
   w.q = (float *)(p + o_q);
   w.b = (uint32_t *)(p + o_b);
+  w.nd = (uint32_t *)(p + o_nd);
+  w.cr = (uint32_t *)(p + o_cr);
   w.cand_cnt = (uint32_t *)(p + o_cc);
   w.queue = (uint32_t *)(p + o_queue);
   w.qlist = (uint32_t *)(p + o_qlist);
@@ -703,7 +713,7 @@ snn_status snn_index::enqueue_merge(const SearchWs &w, const MergeJob &j, hipStr
 snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, hipStream_t s, hipEvent_t *ev) {
   const SearchWs &w = p.w;
   const LearnedPass *lp = o.learned;
-  QueryDesc qd{p.d_ptr, w.cnt, w.status, w.j, w.q, w.b, o.ebase};
+  QueryDesc qd{p.d_ptr, w.cnt, w.nd, w.status, w.j, w.q, w.b, w.cr, o.ebase};
   if (lp) {
     HIP_TRY(this, launch_features(p.nq, p.d_ptr, p.d_c, p.d_v, lp->table, lp->dim, lp->X, s), "feature kernel");
     HIP_TRY(this,
@@ -712,7 +722,8 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
             "mlp forward");
     HIP_TRY(this, launch_threshold(p.nq, lp->yhat, lp->delta, lp->keff_value, lp->thr, lp->keff, s), "threshold");
   }
-  HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, o.max_coords, w.nz_full, s), "prep kernel");
+  HIP_TRY(this, launch_prep(dev, qd, p.nq, p.d_c, p.d_v, o.max_coords, w.nz_full, (const uint32_t *)crow.p, s),
+          "prep kernel");
   HIP_TRY(this, launch_fill_u32((uint32_t *)w.stats, 0u, 8, s), "stats fill");
   TileArgs a{};
   a.ix = dev;

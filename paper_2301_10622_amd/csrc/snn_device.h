@@ -18,6 +18,24 @@
 //                                 value bits) of each document, the vector storage S
 //                                 of Alg. 7; per slot its first entry (uint64) and
 //                                 entry count (uint32)
+//   crow     uint32 [dim]         array-container row of each coordinate, or kNoRow
+//                                 (bitmap container only); set by a compaction
+//   seg      uint32 [rows][nblk+1] per array row and 1,024-slot block, the first entry
+//                                 of the block's segment in `post` (the row's last
+//                                 entry closes it)
+//   post     uint16 [entries]     the posting slots of array rows, as offsets inside
+//                                 their block, in any order within a segment
+//   stale    uint32 [nblk]        non-zero for a block whose postings changed since
+//                                 the last compaction (its array segments are out of
+//                                 date; the bitmaps never are)
+//
+// Containers (the id lists of Section 4.1, Notes on Implementation, held the
+// way Roaring holds them): every coordinate keeps its posting bitmap, which
+// insert and delete update in place; a compaction gives each coordinate of
+// density at most 1/16 an array container as well -- per 1,024-slot block the
+// block offsets of its postings -- so that scoring it costs work per posting
+// rather than per slot. A block changed after the compaction is marked stale
+// and read from the bitmaps.
 //
 // Lane l of a wave owns slots 4l .. 4l+3 of each 256-slot group it covers, so
 // it reads their 4 sketch values with one load and no lane ever contends with
@@ -50,9 +68,13 @@ struct DevIndex {
   float *L;
   uint32_t *slot2id;
   uint32_t *bucket;
+  uint32_t *stale;       // [nblk] blocks changed since the last compaction
+  const uint32_t *seg;   // [rows][nblk + 1] array containers (null before any compaction)
+  const uint16_t *post;
   uint32_t dim, m, h, cap, W;
   uint32_t flags;     // kSketchBf16 | kUpperOnly
 };
+constexpr uint32_t kNoRow = 0xFFFFFFFFu;  // crow of a coordinate with a bitmap container only
 constexpr uint32_t kSketchBf16 = 2u;  // U and L rows hold bfloat16 (U rounded up, L down)
 constexpr uint32_t kUpperOnly = 4u;   // no L half: non-negative collections (Sinnamon+)
 
@@ -73,11 +95,14 @@ struct DevForward {
 struct QueryDesc {
   const uint64_t *qptr;  // [nq + 1] (the caller's CSR offsets; entry e sits at e - ebase below)
   uint32_t *cnt;         // [nq] non-zero entries after preparation
+  uint32_t *nd;          // [nq] of those, the leading entries scored from bitmap containers; the
+                         // rest (array containers) follow in the order of Alg. 6
   uint32_t *status;      // [nq] 0 = ok, else malformed
   uint32_t *j;           // [total]
   float *q;              // [total]
   uint32_t *b;           // [total * h] the buckets pi_o(j); with h = 1 the sketch row
                          // (pi_0(j) << 1) | (q_j < 0), i.e. the bucket and the U / L half
+  uint32_t *cr;          // [total] array-container row of each entry past nd
   uint64_t ebase;        // qptr value of the first entry held in j, q, b
 };
 
@@ -159,9 +184,15 @@ hipError_t launch_serve_mark(uint64_t *vis, uint64_t *dirty, uint32_t n, const u
 hipError_t launch_serve_init(uint64_t *vis, uint64_t *dirty, const uint64_t *live, uint32_t cap, hipStream_t s);
 hipError_t launch_delete(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint64_t *indptr,
                          const uint32_t *coords, int clear_bits, int clear_live, hipStream_t s);
-// max_coords: anytime budget (0 = every coordinate); nz_full (nullable): whole counts
+// max_coords: anytime budget (0 = every coordinate); nz_full (nullable): whole counts;
+// crow (nullable): array-container rows (none: every entry is scored from bitmaps)
 hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint32_t *coords, const float *vals,
-                       uint32_t max_coords, uint32_t *nz_full, hipStream_t s);
+                       uint32_t max_coords, uint32_t *nz_full, const uint32_t *crow, hipStream_t s);
+// compaction: postings per coordinate (cnt[dim]), then the array containers of
+// the coordinates with a row (crow[j] != kNoRow, rows in rbase order)
+hipError_t launch_count_rows(const DevIndex &ix, uint32_t *cnt, hipStream_t s);
+hipError_t launch_build_lists(const DevIndex &ix, uint32_t nrows, const uint32_t *row_coord, const uint64_t *rbase,
+                              uint32_t *seg, uint16_t *post, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);

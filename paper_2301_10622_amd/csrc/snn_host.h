@@ -43,6 +43,7 @@ struct Workspace {
 struct SearchWs {
   uint32_t *cnt = nullptr, *status = nullptr, *thr = nullptr, *fallback = nullptr, *keff = nullptr;
   uint32_t *j = nullptr, *b = nullptr;
+  uint32_t *nd = nullptr, *cr = nullptr;  // bitmap-entry counts; array rows of the other entries
   float *q = nullptr;
   uint32_t *cand_cnt = nullptr, *queue = nullptr;
   uint64_t *cand = nullptr;
@@ -248,6 +249,13 @@ struct snn_index {
   size_t live = 0;
   uint64_t mutations = 0;
 
+  // array containers (snn_compact): crow [dim] (null before the first
+  // compaction), seg and post; the class of every coordinate (1: array)
+  snn::DevBuf crow, lists_seg, lists_post;
+  std::vector<uint8_t> classes;
+  uint32_t list_rows = 0;
+  uint64_t list_postings = 0;
+
   // buffers
   snn::DevBuf up;
   snn::Workspace wsp;
@@ -305,6 +313,7 @@ struct snn_index {
   snn_status search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
                             const float *d_v, uint32_t k, uint32_t max_coords, uint32_t *d_ids, float *d_sc,
                             uint32_t *d_cnt, hipStream_t s);
+  snn_status compact(const uint8_t *pinned);
   void tune_init();
   void release_extras();
 };

@@ -92,12 +92,15 @@ def test_serving_results_equal_alone_at_their_snapshot(qgroup):
         c = int(res_cnt[i])
         parity.check_query(res_ids[i][:c], res_sc[i][:c], s, a, pos_of_id, ids.astype(np.int64), k,
                            what="serve search %d (request %d)" % (i, r))
-    # and a few bit-exactly against the same search alone on a fresh GPU index of that snapshot
+    # and a few bit-exactly against the same search alone on a fresh GPU index
+    # of that snapshot
     for i in pick[:6]:
         r = int(sreq[i])
         _, snap, ids = _oracle_for(states[r])
         alone = P.Index(1000, 32, 1, capacity=max(len(ids), 1), hash_seed=0)
-        P.load_docs(alone, snap, ids=ids)
+        # the same container classes as the serving index (whose blocks changed
+        # in the session are read from the bitmaps): then the same bits
+        P.load_docs(alone, snap, ids=ids, compact=ix.container_classes())
         qc, qv = csr.row(r)
         a_ids, a_sc = alone.search(qc, qv, int(tr["k"][r]))
         c = int(res_cnt[i])
