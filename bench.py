@@ -27,6 +27,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "queries/s at fixed recall@10 (1M docs) + HBM GB/s; learned/batched vs plain; p99"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs, each retiring one wave64 instruction per
+# 4 cycles (16 lanes a cycle) at 2.4 GHz, in lane operations per second (1e12)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(*a):
@@ -231,6 +234,34 @@ def main():
         log("rerank   k=%d k'=%-5d coords %-4s %8.3f ms/step  %10.0f q/s" % (args.k, kp, c or "all", ms,
                                                                           nq / (ms / 1000.0)))
 
+    # the learned filter starting the selection of the k' = 1,000 candidates of
+    # Alg. 7 in place of the sampled first pass (a filter trained for k = k')
+    learned_rr = {}
+    if "learned" in args.forms.split(",") and 1000 in kprimes:
+        tq = gen.make_splade_like(2, docs=0, queries=args.train_queries).queries
+        tt = (torch.tensor(tq.indptr, dtype=torch.int64, device=dev),
+              torch.tensor(tq.coords.astype(np.int32), device=dev), torch.tensor(tq.vals, device=dev))
+        rep = ix.filter_train(*tt, k=1000, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz))
+        del tt
+        filters["k1000"] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rep.items()}
+        out = (torch.empty((nq, args.k), dtype=torch.int32, device=dev),
+               torch.empty((nq, args.k), dtype=torch.float32, device=dev), torch.empty(nq, dtype=torch.int32, device=dev))
+        for _ in range(args.warmup):
+            ix.search_ex_dev(ip, qc, qv, args.k, mode=P.MODE_LEARNED, k_prime=1000, out=out, total=total)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ix.search_ex_dev(ip, qc, qv, args.k, mode=P.MODE_LEARNED, k_prime=1000, out=out, total=total)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        fb = ix.last_batch_status()[1]
+        ref = outs[("rerank", 1000, 0)]
+        same = all(bool(torch.equal(a, b)) for a, b in zip(out, ref))
+        learned_rr = {"qps": nq / (ms / 1000.0), "ms_per_step": ms, "steps": args.steps, "fallbacks_last_step": fb,
+                      "identical_to_batched_rerank": same}
+        log("learned  k=%d k'=1000 %8.3f ms/step  %10.0f q/s  fallbacks %d  identical to the batched re-rank %s" % (
+            args.k, ms, nq / (ms / 1000.0), fb, same))
+
     # the same batch through the host-buffer call (host validation, upload over
     # PCIe, the batched search, results back): context, never the headline
     qh = w.queries
@@ -258,13 +289,14 @@ def main():
     if not args.no_variants:
         ix.close()
         torch.cuda.empty_cache()
-        for vname, bf, up in (("bf16", True, False), ("upper_only", False, True), ("bf16_upper_only", True, True)):
-            vx = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
+        for vname, bf, up, hv in (("bf16", True, False, w.h), ("upper_only", False, True, w.h),
+                                  ("bf16_upper_only", True, True, w.h), ("h2", False, False, 2)):
+            vx = P.Index(w.n, w.m, hv, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
                          forward_store=True, sketch_bf16=bf, upper_only=up)
             P.load_docs(vx, w.docs, compact=not args.no_compact)
             vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]),
                             sched["qgroup"])
-            r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2)}
+            r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2), "h": hv}
             for form, kw in (("batched_k10", dict(k_prime=0, max_coords=0)),
                              ("rerank_k1000_coords10", dict(k_prime=1000, max_coords=10))):
                 out = (torch.empty((nq, args.k), dtype=torch.int32, device=dev),
@@ -292,15 +324,34 @@ def main():
     launch_ms = head["tile_kernel_ms_per_launch"]
     per_launch_queries = nq / head["tile_launches_per_step"]
     ab_launch = alg_bytes(args.k) * per_launch_queries / nq
-    achieved = ab_launch / (launch_ms / 1000.0) / 1e9
     kname = tile_kernel_name(sched, best)
-    traffic = measured_traffic(kname, args.k)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                "alg_bytes_per_launch": ab_launch, "launch_ms": launch_ms}
+    ctr = measured_counters(kname, args.k)
+    traffic = ctr.get("traffic_bytes_per_launch") if ctr else None
+    comp = compulsory_bytes(np, w, ix.container_classes(), list_len, ix.bucket_table().reshape(w.h, w.n))
+    comp_launch = comp * per_launch_queries / nq
+    launch_s = launch_ms / 1000.0
+    if ctr and ctr.get("valu_insts_per_launch"):
+        # the bound the kernel reaches: VALU issue (one wave instruction per
+        # SIMD every 4 cycles, i.e. 16 lane operations per SIMD and cycle)
+        achieved = ctr["valu_insts_per_launch"] * 64 / launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS,
+                    "unit": "T VALU lane-ops/s", "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                    "valu_insts_per_launch": ctr["valu_insts_per_launch"]}
+    else:
+        # counters not taken on this kernel source: the compulsory bytes of the
+        # launch against the HBM peak
+        achieved = comp_launch / launch_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic}
+    roofline.update({"kernel": kname, "launch_ms": launch_ms, "counters_match_source": bool(ctr),
+                     "compulsory_bytes_per_launch": comp_launch,
+                     "compulsory_GBps": round(comp_launch / launch_s / 1e9, 1),
+                     "alg_bytes_per_launch": ab_launch,
+                     "alg_GBps_effective": round(ab_launch / launch_s / 1e9, 1)})
     if traffic:
-        roofline["traffic_GBps"] = round(traffic / (launch_ms / 1000.0) / 1e9, 1)
-        roofline["traffic_over_alg_bytes"] = round(traffic / ab_launch, 4)
+        roofline["traffic_GBps"] = round(traffic / launch_s / 1e9, 1)
+        roofline["hbm_frac_traffic"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["traffic_over_compulsory"] = round(traffic / comp_launch, 3)
     # what this machine's HBM delivers to a plain device copy, beside the published peak
     roofline["copy_GBps"] = round(measured_copy_gbps(torch, dev), 1)
 
@@ -410,6 +461,11 @@ def main():
         result["sketch_variants"] = {v: {f: ({kk: (round(x, 4) if isinstance(x, float) else x) for kk, x in d.items()}
                                              if isinstance(d, dict) else d) for f, d in r.items()}
                                      for v, r in variants_res.items()}
+    if learned_rr:
+        if (1000, 0) in rerank and "recall_at_%d" % args.k in rerank[(1000, 0)]:
+            learned_rr["recall_at_%d" % args.k] = rerank[(1000, 0)]["recall_at_%d" % args.k]
+        learned_rr["learned_over_batched"] = round(learned_rr["qps"] / rerank[(1000, 0)]["qps"], 4)
+        result["learned_rerank_k1000"] = _rounded(learned_rr)
     if rerank:
         result["rerank"] = {("k'=%d" % kp) + ("" if not c else " coords=%d" % c):
                             {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in r.items()}
@@ -547,32 +603,34 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, k):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    passes (calibrated against a plain copy), or None when the kernel source has
+def measured_counters(kernel, k):
+    """Per-launch figures of the committed rocprofv3 passes for this kernel and
+    k (HBM bytes from FETCH_SIZE / WRITE_SIZE calibrated against a plain copy,
+    VALU instructions from SQ_INSTS_VALU), or None when the kernel source has
     changed since they were taken."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
-    if not rec:
+    if not rec or kernel_source_sha256() != rec["source_sha256"]:
         return None
-    if kernel_source_sha256() != rec["source_sha256"]:
-        return None
-    if k == 100 and "k100" in rec:
-        return rec["k100"]["traffic_bytes_per_launch"]
-    return rec["traffic_bytes_per_launch"] if k == 10 else None
+    return rec.get("k%d" % k)
 
 
-def recall_vs_exact(ora, queries, ids, cnt, k, threads):
-    """Mean recall@k of the GPU results (ids, counts: numpy rows of `queries`)
-    against the oracle's exact brute-force top-k (Eq. 2)."""
-    import numpy as np
-
-    eids, _, _, ecnt = ora.search(queries, k, exact=True, threads=threads)
-    r = [len(set(ids[i][: cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist())) / max(1, min(k, ecnt[i]))
-         for i in range(queries.rows)]
-    return float(np.mean(r))
+def compulsory_bytes(np, w, classes, list_len, buckets, sketch_bytes=4):
+    """HBM bytes a batch of the workload must read at least once: the posting
+    containers of every distinct query coordinate (a bitmap over the used slots,
+    or an array container: 2 bytes per posting plus its row of block offsets),
+    every sketch row (bucket, U or L half) a query entry touches, over the used
+    slots, the live bitmap, and 16 bytes per prepared query entry."""
+    used = -(-w.docs.rows // 1024) * 1024
+    qc = w.queries.coords.astype(np.int64)
+    j = np.unique(qc)
+    arr = classes[j] != 0
+    cont = float(np.sum(np.where(arr, 2 * list_len[j] + (used // 1024 + 1) * 4, used // 8)))
+    neg = (w.queries.vals < 0).astype(np.int64)
+    rows = np.unique(np.concatenate([buckets[o][qc].astype(np.int64) * 2 + neg for o in range(len(buckets))]))
+    return cont + float(len(rows)) * used * sketch_bytes + used / 8 + 16.0 * len(qc)
 
 
 def _rounded(d):
@@ -631,7 +689,7 @@ def batch_4m(args, dev, P, gen, np, torch):
 
 
 def paper_gaussian(args, dev, P, gen, np, torch, psi):
-    """The real-valued collections of Section 6.5 (Table 6): 5M docs, every
+    """The real-valued collections of Section 6.5 (Table 4): 5M docs, every
     coordinate non-zero with probability psi / n, N(0, 1) values; k = 1,000 and
     k' = 20,000, 2m = 74 (G100) or 150 (G200), h = 1, as the paper runs them. The
     anytime budget is a count of coordinates here (the paper's T is in ms).
@@ -720,7 +778,7 @@ def paper_gaussian(args, dev, P, gen, np, torch, psi):
         res["forms"][name]["overlap_with_oracle_alg7"] = round(float(np.mean(same)), 4)
         log("g%d %s: recall@%d %.4f, id overlap with the oracle's Alg. 7 %.4f (%d queries)" % (
             psi, name, k, np.mean(rec), np.mean(same), S))
-    res["paper_table6_context"] = ("CPU (the paper's Intel setup), Sinnamon 2m=%d: T=40 ms -> %s, T=20 ms -> %s" %
+    res["paper_table4_context"] = ("CPU (the paper's Intel setup), Sinnamon 2m=%d: T=40 ms -> %s, T=20 ms -> %s" %
                                    ((74, "87 ms, recall 0.97", "66 ms, recall 0.89") if psi == 100 else
                                     (150, "107 ms, recall 0.92", "86 ms, recall 0.83")))
     del ora

@@ -200,9 +200,13 @@ snn_status snn_search_batch_dev_noalloc(snn_index *ix, uint32_t nq, const uint64
 /* Options of one batch search (all the forms above in one call):
  *   mode        SNN_MODE_PLAIN, SNN_MODE_BATCHED or SNN_MODE_LEARNED
  *   k_prime     0: ranking by the Sinnamon scores (Alg. 7 with k' = k, i.e.
- *               Alg. 3); k <= k_prime <= 4096: Alg. 7 with k_prime candidates
- *               re-scored exactly (SNN_MODE_BATCHED and an index with
- *               SNN_FORWARD_STORE)
+ *               Alg. 3); k <= k_prime <= 65,536: Alg. 7 with k_prime
+ *               candidates re-scored exactly (an index with
+ *               SNN_FORWARD_STORE; SNN_MODE_BATCHED, or SNN_MODE_LEARNED,
+ *               where the filter's threshold -- trained with k = k_prime --
+ *               starts the selection of the k_prime candidates and a query
+ *               that keeps fewer runs again without it, so the results are
+ *               those of SNN_MODE_BATCHED)
  *   max_coords  0: every query coordinate is scored; c > 0: the anytime
  *               variant, scoring stops after the first c coordinates in the
  *               order of Alg. 6 (|q_j| descending, ties by the lower j). This
@@ -219,8 +223,9 @@ typedef struct {
 
 /* Device-pointer batch search with options; arguments otherwise as in
  * snn_search_batch_dev. Errors: SNN_E_INVALID (k = 0 or > 4096, nq = 0, an
- * unknown mode, 0 < k' < k, k' > 65,536, re-rank outside SNN_MODE_BATCHED or
- * without a forward store, reserved != 0), SNN_E_NOMEM, SNN_E_DEVICE. */
+ * unknown mode, 0 < k' < k, k' > 65,536, re-rank in SNN_MODE_PLAIN or
+ * without a forward store, no trained filter for SNN_MODE_LEARNED, reserved
+ * != 0), SNN_E_NOMEM, SNN_E_DEVICE. */
 snn_status snn_search_ex_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr, uint64_t total,
                              const uint32_t *coords, const float *vals, uint32_t k, const snn_search_params *params,
                              uint32_t *out_ids, float *out_scores, uint32_t *out_counts, void *stream);

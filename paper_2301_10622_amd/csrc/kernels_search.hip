@@ -235,17 +235,22 @@ __device__ __forceinline__ float gather_bound(const DevIndex &ix, cptr<uint32_t>
 
 // sp: the wave's 256 G scores in LDS (slot wslot0 + x at sp[x]); sets them to
 // the sums of the terms of entries [e_begin, e_end).
-template <int R, bool kBf16, int SC, bool kH1>
+//
+// The segment bounds of up to 64 entries in the block are read at once, lane t
+// holding entry t's (one vector load each, no scalar round trip per entry);
+// then CH entries at a time, the wave requests every offset and every bound of
+// the CH segments before the first add, so CH entries share one pair of memory
+// round trips, and adds them entry by entry.
+template <int R, bool kBf16, bool kH1>
 __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end, uint32_t wslot0, float *sp) {
   constexpr int G = R / 4;
   constexpr uint32_t kSpan = 256u * G;  // slots of the wave
-  const int lane = threadIdx.x & 63;
+  constexpr int CH = 8;                 // entries whose loads are in flight together
+  const uint32_t lane = threadIdx.x & 63;
   const DevIndex &ix = a.ix;
   const cptr<uint32_t> qj = as_const(a.qd.j);
   const cptr<float> qq = as_const(a.qd.q);
   const cptr<uint32_t> qb = as_const(a.qd.b);
-  const cptr<uint32_t> qc = as_const(a.qd.cr);
-  const cptr<uint32_t> sg = as_const(ix.seg);
   const uint32_t h = ix.h;
   const uint32_t nblk1 = (ix.cap >> 10) + 1u;
 #pragma unroll
@@ -267,37 +272,44 @@ __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end
       }
     };
     if (as_const(ix.stale)[blk] == 0u) {
-      for (uint64_t e = e_begin; e < e_end; e += SC) {
-        // the chunk's segments, offsets and bounds are all requested before
-        // the first add; the adds then go entry by entry
-        uint32_t s0[SC], n[SC], off[SC];
-        float qv[SC], v[SC];
-#pragma unroll
-        for (int k = 0; k < SC; ++k) {
-          const bool in = e + k < e_end;
-          const uint64_t ek = in ? e + k : e;
-          const size_t rb = (size_t)qc[ek] * nblk1 + blk;
-          s0[k] = sg[rb];
-          n[k] = in ? sg[rb + 1] - s0[k] : 0u;
-          qv[k] = qq[ek];
+      for (uint64_t eb = e_begin; eb < e_end; eb += 64) {
+        const uint32_t ne = (uint32_t)min((uint64_t)64, e_end - eb);
+        uint32_t vs0 = 0, vn = 0;  // lane t: entry eb + t's segment start and length
+        if (lane < ne) {
+          const size_t rb = (size_t)a.qd.cr[eb + lane] * nblk1 + blk;
+          vs0 = ix.seg[rb];
+          vn = ix.seg[rb + 1] - vs0;
         }
+        for (uint32_t c0 = 0; c0 < ne; c0 += CH) {
+          uint32_t s0[CH], n[CH], off[CH];
+          float qv[CH], v[CH];
 #pragma unroll
-        for (int k = 0; k < SC; ++k) {
-          off[k] = (uint32_t)lane < n[k] ? (uint32_t)ix.post[s0[k] + lane] : 0xFFFFu;
-          const bool mine = off[k] >= lo && off[k] < hi;
-          v[k] = mine ? gather_bound<kBf16, kH1>(ix, qb, e + k, h, qv[k] > 0.0f, bslot0 + off[k]) : 0.0f;
-        }
+          for (int k = 0; k < CH; ++k) {
+            const bool in = c0 + k < ne;
+            const uint32_t t = in ? c0 + (uint32_t)k : 0u;
+            s0[k] = __builtin_amdgcn_readlane(vs0, t);
+            n[k] = in ? __builtin_amdgcn_readlane(vn, t) : 0u;
+            qv[k] = qq[eb + t];
+            off[k] = lane < n[k] ? (uint32_t)ix.post[s0[k] + lane] : 0xFFFFu;
+          }
 #pragma unroll
-        for (int k = 0; k < SC; ++k) {
-          if (off[k] >= lo && off[k] < hi) spb[off[k] - lo] = __builtin_fmaf(qv[k], v[k], spb[off[k] - lo]);
-          __builtin_amdgcn_wave_barrier();
-          // the rest of a segment longer than one wave step (rare: the class
-          // is chosen for at most 64 postings per block on average), before
-          // the next entry's adds
-          for (uint32_t p0 = 64; p0 < n[k]; p0 += 64) {
-            const uint32_t o = p0 + (uint32_t)lane < n[k] ? (uint32_t)ix.post[s0[k] + p0 + lane] : 0xFFFFu;
-            add(e + k, qv[k], o);
+          for (int k = 0; k < CH; ++k) {
+            const bool mine = off[k] >= lo && off[k] < hi;
+            v[k] = mine ? gather_bound<kBf16, kH1>(ix, qb, eb + c0 + k, h, qv[k] > 0.0f, bslot0 + off[k]) : 0.0f;
+          }
+#pragma unroll
+          for (int k = 0; k < CH; ++k) {
+            if (n[k] == 0u) continue;
+            if (off[k] >= lo && off[k] < hi) spb[off[k] - lo] = __builtin_fmaf(qv[k], v[k], spb[off[k] - lo]);
             __builtin_amdgcn_wave_barrier();
+            // the rest of a segment longer than one wave step (rare: the class
+            // is chosen for at most 64 postings per block on average), before
+            // the next entry's adds
+            for (uint32_t p0 = 64; p0 < n[k]; p0 += 64) {
+              const uint32_t o = p0 + lane < n[k] ? (uint32_t)ix.post[s0[k] + p0 + lane] : 0xFFFFu;
+              add(eb + c0 + k, qv[k], o);
+              __builtin_amdgcn_wave_barrier();
+            }
           }
         }
       }
@@ -311,7 +323,7 @@ __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end
         while (bits) {
           const uint32_t x = (uint32_t)__builtin_ctz(bits);
           bits &= bits - 1u;
-          add(e, q, 256u * (x >> 2) + 4u * (uint32_t)lane + (x & 3u));
+          add(e, q, 256u * (x >> 2) + 4u * lane + (x & 3u));
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -439,7 +451,7 @@ __device__ void tile_body(const TileArgs &a, uint32_t q, uint32_t t, SelShared &
     }
   }
   if (nd < ne) {
-    score_arrays<R, kBf16, (R <= 16 ? 4 : 64 / R), false>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
+    score_arrays<R, kBf16, false>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
     fold_arrays<R>(sp + wave * 64 * R, acc);
   }
 
@@ -673,7 +685,7 @@ __device__ void tile_group(const TileArgs &a, uint32_t grp, uint32_t t, uint32_t
         en = aend[ii];
       }
     if (b < en) {
-      score_arrays<R, kBf16, 4, true>(a, b, en, wslot0, sp + wave * 64 * R);
+      score_arrays<R, kBf16, true>(a, b, en, wslot0, sp + wave * 64 * R);
 #pragma unroll
       for (int ii = 0; ii < Q; ++ii)
         if (ii == i) fold_arrays<R>(sp + wave * 64 * R, acc[ii]);
@@ -755,7 +767,7 @@ __device__ void tile_body_latency(const TileArgs &a, uint32_t q, uint32_t t, Sel
     for (int k = 0; k < PC; ++k) cb[k] = nb[k];
   }
   if (nd < ne) {
-    score_arrays<R, kBf16, (R <= 16 ? 8 : 64 / R), true>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
+    score_arrays<R, kBf16, true>(a, e0 + nd, e0 + ne, wslot0, sp + wave * 64 * R);
     fold_arrays<R>(sp + wave * 64 * R, acc);
   }
   finish<R>(a, q, t, acc, sh);
@@ -850,13 +862,13 @@ __global__ __launch_bounds__(kBlock) void k_tiles_grouped(TileArgs a) {
   tile_group<R, kBf16, Q>(a, grp, blockIdx.x, nq, sh, sp);
 }
 
-// Waves per SIMD the persistent grouped kernel is built for: with R = 16, two
-// queries and a float32 sketch the register file holds 8 (64 VGPRs, a few
-// spilled around the selection), which is measurably faster than 7; the other
-// shapes, bfloat16 included, are left to the compiler (they are slower at 8).
+// Waves per SIMD the persistent grouped kernel is built for: left to the
+// compiler. (Before the array containers, R = 16 with two queries was built
+// for 8 waves at 64 VGPRs, 2.4% faster than 7; with the array path that cap
+// spills in the scoring loop, and 6 waves are 7% faster than 8.)
 template <int R, bool kBf16, int Q>
 struct GroupedWaves {
-  static constexpr int value = (R == 16 && Q == 2 && !kBf16) ? 8 : 1;
+  static constexpr int value = 1;
 };
 
 template <int R, bool kBf16, int Q>

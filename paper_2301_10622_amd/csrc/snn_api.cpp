@@ -1051,7 +1051,8 @@ static snn_status check_params(snn_index *ix, uint32_t k, const snn_search_param
     if (p.k_prime < k) return ix->fail(SNN_E_INVALID, "re-rank: need k <= k' (k = %u, k' = %u)", k, p.k_prime);
     if (!ix->has_fwd) return ix->fail(SNN_E_INVALID, "re-rank: the index has no forward store (SNN_FORWARD_STORE)");
     if (p.k_prime > kMaxKPrime) return ix->fail(SNN_E_INVALID, "re-rank: k' must be <= %u", kMaxKPrime);
-    if (p.mode != SNN_MODE_BATCHED) return ix->fail(SNN_E_INVALID, "re-rank: runs in SNN_MODE_BATCHED only");
+    if (p.mode == SNN_MODE_PLAIN)
+      return ix->fail(SNN_E_INVALID, "re-rank: runs in SNN_MODE_BATCHED or SNN_MODE_LEARNED");
   }
   return SNN_OK;
 }
@@ -1063,8 +1064,12 @@ static snn_status search_dev(snn_index *ix, uint32_t nq, const uint64_t *indptr,
                              hipStream_t s) {
   ix->last_nq = nq;
   ix->last_mode = p.mode;
-  if (p.mode == SNN_MODE_LEARNED)
-    return ix->search_learned(nq, indptr, total, coords, vals, k, p.max_coords, out_ids, out_scores, out_counts, s);
+  if (p.mode == SNN_MODE_LEARNED) {
+    // with k' > k the filter's threshold starts the selection of the k' candidates
+    const uint32_t kb = p.k_prime ? p.k_prime : k;
+    return ix->search_learned(nq, indptr, total, coords, vals, kb, p.max_coords, p.k_prime ? k : 0u,
+                              p.k_prime ? rerank_hash_cap(max_nnz) : 0u, out_ids, out_scores, out_counts, s);
+  }
   SearchOpts o;
   o.max_coords = p.max_coords;
   uint32_t kb = k;

@@ -228,7 +228,12 @@ extern "C" snn_status snn_filter_train(snn_index *ix, uint32_t nq, const uint64_
 
   // 2. labels ln(s_k) from the plain method, in chunks
   const uint32_t k = pr->k;
-  const uint32_t chunk = 16384;
+  // queries per labelling search: the tile candidates of a chunk (tiles x
+  // min(k, tile) x 8 bytes per query) stay within about 2 GiB
+  const uint64_t tile_docs = (uint64_t)kBlock * (uint64_t)std::max(16, ix->tune.R_batch);
+  const uint64_t tiles = std::max<uint64_t>(1, (ix->next_fresh + tile_docs - 1) / tile_docs);
+  const uint64_t per_query = tiles * std::min<uint64_t>(k, tile_docs) * 8;
+  const uint32_t chunk = (uint32_t)std::max<uint64_t>(256, std::min<uint64_t>(16384, (2ull << 30) / per_query));
   DevBuf lab;
   HIP_TRY(ix, lab.ensure((size_t)chunk * k * 8 + (size_t)chunk * 4 + 256, s), "label buffers");
   HIP_TRY(ix, f->ty.ensure((size_t)nq * 4, s), "labels");
@@ -360,9 +365,11 @@ extern "C" snn_status snn_filter_train(snn_index *ix, uint32_t nq, const uint64_
 // ---------------------------------------------------------------------------
 // filtered search with fallback
 // ---------------------------------------------------------------------------
+// k: the selection's k (k' when re-ranking, then rerank_k results are kept)
 snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
-                                     const float *d_v, uint32_t k, uint32_t max_coords, uint32_t *d_ids, float *d_sc,
-                                     uint32_t *d_cnt, hipStream_t s) {
+                                     const float *d_v, uint32_t k, uint32_t max_coords, uint32_t rerank_k,
+                                     uint32_t hash_cap, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt,
+                                     hipStream_t s) {
   LearnedFilter *f = filter;
   if (!f || !f->ready) return fail(SNN_E_INVALID, "search: no trained filter (call snn_filter_train first)");
   HIP_TRY(this, f->X.ensure((size_t)nq * kFeat * 4, s), "features");
@@ -382,6 +389,8 @@ snn_status snn_index::search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_
   SearchOpts o;
   o.learned = &lp;
   o.max_coords = max_coords;
+  o.rerank_k = rerank_k;
+  o.hash_cap = hash_cap;
   return run_search(nq, d_ptr, total, d_c, d_v, k, SNN_MODE_LEARNED, d_ids, d_sc, d_cnt, s, o);
 }
 

@@ -311,8 +311,8 @@ struct snn_index {
                         uint32_t k, int mode, uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s,
                         const snn::SearchOpts &o);
   snn_status search_learned(uint32_t nq, const uint64_t *d_ptr, uint64_t total, const uint32_t *d_c,
-                            const float *d_v, uint32_t k, uint32_t max_coords, uint32_t *d_ids, float *d_sc,
-                            uint32_t *d_cnt, hipStream_t s);
+                            const float *d_v, uint32_t k, uint32_t max_coords, uint32_t rerank_k, uint32_t hash_cap,
+                            uint32_t *d_ids, float *d_sc, uint32_t *d_cnt, hipStream_t s);
   snn_status compact(const uint8_t *pinned);
   void tune_init();
   void release_extras();

@@ -297,3 +297,52 @@ def test_learned_after_mutations_stays_identical(trained):
     learned = _dev_search(ix, t, 10, P.MODE_LEARNED)
     for a, b in zip(plain, learned):
         assert np.array_equal(a, b)
+
+
+def test_learned_threshold_starts_the_rerank_selection():
+    """Alg. 7 with k = 10 and k' = 1,000 on 300,000 documents (73 tiles, so the
+    batched form samples a sixteenth of the tiles first): a filter trained for
+    k = 1,000 starts the k' selection instead, with the device-side fallback.
+    Results are those of the batched form bit for bit, and pass the Alg. 7
+    check against the oracle; on the GPU's own counters the learned pass kept
+    at most 10 k' candidates per query (73 k' without a threshold) while about
+    5% of the queries fell back."""
+    import torch
+
+    import paper_2301_10622_amd as P
+
+    docs = gen.small_docs(41, 300_000)
+    ix = P.Index(1000, 32, 1, capacity=docs.rows, hash_seed=0, forward_store=True)
+    P.load_docs(ix, docs)
+    tq = gen.serving_queries(42, 20_000)
+    rep = ix.filter_train(*_dev(tq), k=1000, epochs=6, batch=512, lr=1e-3)
+    assert rep["holdout_fallback"] <= 0.1, rep
+    q = gen.serving_queries(43, 512)
+    t = _dev(q)
+
+    def run(mode):
+        ids, sc, cnt = ix.search_ex_dev(*t, 10, mode=mode, k_prime=1000)
+        torch.cuda.synchronize()
+        return ids.cpu().numpy().copy(), sc.cpu().numpy().copy(), cnt.cpu().numpy().copy()
+
+    batched = run(P.MODE_BATCHED)
+    learned = run(P.MODE_LEARNED)
+    _, fb = ix.last_batch_status()
+    work = ix.last_batch_work()
+    for a, b in zip(batched, learned):
+        assert np.array_equal(a, b)
+    assert 0 < fb <= 0.15 * q.rows, fb
+    # without a starting threshold every tile hands over min(k', tile) = 1,000
+    # candidates per query (73 tiles: 73,000); the learned threshold lets
+    # through fewer than a seventh of that before the fallback re-runs
+    assert work["candidates"] <= 10 * 1000 * q.rows, work
+    ora = O.Index(docs, 1000, 32, 1, 0)
+    ids_of_pos = ora.ids.astype(np.int64)
+    for qi in range(0, q.rows, 32):
+        qc, qv = q.row(qi)
+        est, ea = ora.score_all(qc, qv)
+        ex, xa = ora.score_all(qc, qv, exact=True)
+        n = int(learned[2][qi])
+        parity.check_rerank_query(learned[0][qi][:n], learned[1][qi][:n], est, ea, ex, xa, ids_of_pos, 10, 1000,
+                                  what="learned rerank q%d" % qi)
+    ix.close()
