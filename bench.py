@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--forms", default="plain,batched,learned")
     ap.add_argument("--train-queries", type=int, default=50000)
+    ap.add_argument("--filter-fallback", type=float, default=0.01,
+                    help="share of held-out queries whose predicted threshold may exceed their k-th score")
     ap.add_argument("--no-small", action="store_true", help="skip the learned-filter workload on the 10k-doc index")
     ap.add_argument("--no-batch4m", action="store_true", help="skip the 4M-doc batching workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the 8M-capacity serving workload")
@@ -57,7 +59,7 @@ def main():
     ap.add_argument("--no-g100", action="store_true", help="skip the G100 workload of the paper (Section 6.5)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the bfloat16 / upper-only sketch variants of the 1M-doc index")
-    ap.add_argument("--g200", action="store_true", help="also run the G200 workload (20 GB of bitmaps)")
+    ap.add_argument("--no-g200", action="store_true", help="skip the G200 workload of the paper (Section 6.5)")
     ap.add_argument("--anytime", default="5,10,20",
                     help="coordinate budgets of the anytime re-ranking forms (k' = 1000); empty to skip")
     ap.add_argument("--serving-ops", type=int, default=100_000)
@@ -196,7 +198,8 @@ def main():
                 tq = gen.make_splade_like(2, docs=0, queries=args.train_queries).queries
                 tt = (torch.tensor(tq.indptr, dtype=torch.int64, device=dev),
                       torch.tensor(tq.coords.astype(np.int32), device=dev), torch.tensor(tq.vals, device=dev))
-                rep = ix.filter_train(*tt, k=k, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz))
+                rep = ix.filter_train(*tt, k=k, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz),
+                                      target_fallback=args.filter_fallback)
                 filters["k%d" % k] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rep.items()}
                 log("filter k=%d trained: %s" % (k, filters["k%d" % k]))
                 del tt
@@ -234,6 +237,10 @@ def main():
         log("rerank   k=%d k'=%-5d coords %-4s %8.3f ms/step  %10.0f q/s" % (args.k, kp, c or "all", ms,
                                                                           nq / (ms / 1000.0)))
 
+    # the headline index's container classes and mappings (for the compulsory bytes)
+    main_classes = ix.container_classes()
+    main_buckets = ix.bucket_table().reshape(w.h, w.n)
+
     # the learned filter starting the selection of the k' = 1,000 candidates of
     # Alg. 7 in place of the sampled first pass (a filter trained for k = k')
     learned_rr = {}
@@ -241,7 +248,8 @@ def main():
         tq = gen.make_splade_like(2, docs=0, queries=args.train_queries).queries
         tt = (torch.tensor(tq.indptr, dtype=torch.int64, device=dev),
               torch.tensor(tq.coords.astype(np.int32), device=dev), torch.tensor(tq.vals, device=dev))
-        rep = ix.filter_train(*tt, k=1000, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz))
+        rep = ix.filter_train(*tt, k=1000, epochs=8, batch=512, lr=1e-3, total=int(tq.nnz),
+                              target_fallback=args.filter_fallback)
         del tt
         filters["k1000"] = {kk: (round(v, 4) if isinstance(v, float) else v) for kk, v in rep.items()}
         out = (torch.empty((nq, args.k), dtype=torch.int32, device=dev),
@@ -294,8 +302,9 @@ def main():
             vx = P.Index(w.n, w.m, hv, capacity=w.docs.rows, hash_seed=w.hash_seed, stream=stream,
                          forward_store=True, sketch_bf16=bf, upper_only=up)
             P.load_docs(vx, w.docs, compact=not args.no_compact)
-            vx.set_schedule(sched["R_plain"], sched["R_batch"], sched["grid"], bool(sched["persistent"]),
-                            sched["qgroup"])
+            # several queries per workgroup need h = 1
+            vx.set_schedule(sched["R_plain"], max(16, sched["R_batch"]) if hv != 1 else sched["R_batch"],
+                            sched["grid"], bool(sched["persistent"]), sched["qgroup"] if hv == 1 else 1)
             r = {"sketch_bytes": w.m * w.docs.rows * (2 if bf else 4) * (1 if up else 2), "h": hv}
             for form, kw in (("batched_k10", dict(k_prime=0, max_coords=0)),
                              ("rerank_k1000_coords10", dict(k_prime=1000, max_coords=10))):
@@ -327,7 +336,7 @@ def main():
     kname = tile_kernel_name(sched, best)
     ctr = measured_counters(kname, args.k)
     traffic = ctr.get("traffic_bytes_per_launch") if ctr else None
-    comp = compulsory_bytes(np, w, ix.container_classes(), list_len, ix.bucket_table().reshape(w.h, w.n))
+    comp = compulsory_bytes(np, w, main_classes, list_len, main_buckets)
     comp_launch = comp * per_launch_queries / nq
     launch_s = launch_ms / 1000.0
     if ctr and ctr.get("valu_insts_per_launch"):
@@ -484,7 +493,7 @@ def main():
         result["batch_4m"] = batch_4m(args, dev, P, gen, np, torch)
     if not args.no_g100:
         result["g100"] = paper_gaussian(args, dev, P, gen, np, torch, 100)
-    if args.g200:
+    if not args.no_g200:
         result["g200"] = paper_gaussian(args, dev, P, gen, np, torch, 200)
     if not args.no_serving:
         result["serving_8m"] = serving_8m(args, dev, P, gen, np, torch)
@@ -633,6 +642,17 @@ def compulsory_bytes(np, w, classes, list_len, buckets, sketch_bytes=4):
     return cont + float(len(rows)) * used * sketch_bytes + used / 8 + 16.0 * len(qc)
 
 
+def recall_vs_exact(ora, queries, ids, cnt, k, threads):
+    """Mean recall@k of the GPU results (ids, counts: numpy rows of `queries`)
+    against the oracle's exact brute-force top-k (Eq. 2)."""
+    import numpy as np
+
+    eids, _, _, ecnt = ora.search(queries, k, exact=True, threads=threads)
+    r = [len(set(ids[i][: cnt[i]].tolist()) & set(eids[i][: ecnt[i]].tolist())) / max(1, min(k, ecnt[i]))
+         for i in range(queries.rows)]
+    return float(np.mean(r))
+
+
 def _rounded(d):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
 
@@ -719,7 +739,12 @@ def paper_gaussian(args, dev, P, gen, np, torch, psi):
            "insert_docs_per_s_host_api": round(w.docs.rows / t_ins, 1), "forms": {}}
     # the batched schedule, tuned on the first batch at k = 1,000
     ip0, qc0, qv0, _ = batches[0]
-    res["schedule"] = ix.autotune(ip0, qc0, qv0, k, total=int(qc0.numel()))
+    if args.schedule:
+        R, Q, grid, pers = [int(x) for x in args.schedule.split(",")]
+        ix.set_schedule(16, R, grid, bool(pers), Q)
+        res["schedule"] = ix.schedule()
+    else:
+        res["schedule"] = ix.autotune(ip0, qc0, qv0, k, total=int(qc0.numel()))
     log("g%d: schedule %s" % (psi, res["schedule"]))
     outs = {}
     budgets = (0, 50, 25) if psi == 100 else (0, 100, 50)
@@ -859,7 +884,7 @@ def small_learned(args, dev, P, gen, np, torch):
                     torch.tensor(q.coords.astype(np.int32), device=dev), torch.tensor(q.vals, device=dev))
     tt, et = up(tq), up(eq)
     sched = ix.autotune(*et, 10)
-    rep = ix.filter_train(*tt, k=10, epochs=8, batch=1024, lr=1e-3)
+    rep = ix.filter_train(*tt, k=10, epochs=8, batch=1024, lr=1e-3, target_fallback=args.filter_fallback)
     log("small: filter trained: %s" % rep)
     nq = eq.rows
     out = (torch.empty((nq, 10), dtype=torch.int32, device=dev), torch.empty((nq, 10), dtype=torch.float32, device=dev),

@@ -45,41 +45,47 @@ __device__ __forceinline__ uint16_t bf16_round(float x, bool up) {
   return (uint16_t)t;
 }
 
-__global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const uint32_t *__restrict__ slots,
-                                               const uint32_t *__restrict__ ids,
-                                               const uint64_t *__restrict__ indptr,
-                                               const uint32_t *__restrict__ coords,
-                                               const float *__restrict__ vals, DevForward fw,
-                                               const uint64_t *__restrict__ doc_off) {
-  extern __shared__ uint32_t ins_lds[];  // 2m words: running max keys, then min keys
-  const uint32_t d = upd_doc(n);
-  if (d >= n) return;
-  uint32_t *umax = ins_lds;
-  uint32_t *umin = ins_lds + ix.m;
-  const int lane = threadIdx.x;
+// Steps 1, 2 and 4 above for document d (with `postings`, step 3's posting
+// bits too, one atomic each), a wave per document; umax / umin are the wave's
+// m LDS keys each. Every wave of the workgroup calls it the same number of
+// times (a wave without a document passes active = false), since it holds
+// workgroup barriers.
+__device__ __forceinline__ void insert_doc(const DevIndex &ix, bool active, uint32_t d,
+                                           const uint32_t *__restrict__ slots, const uint32_t *__restrict__ ids,
+                                           const uint64_t *__restrict__ indptr, const uint32_t *__restrict__ coords,
+                                           const float *__restrict__ vals, const DevForward &fw,
+                                           const uint64_t *__restrict__ doc_off, uint32_t *umax, uint32_t *umin,
+                                           bool postings) {
+  const uint32_t lane = threadIdx.x & 63;
   const uint32_t m = ix.m, h = ix.h;
   for (uint32_t b = lane; b < m; b += 64) {
     umax[b] = 0u;           // below every finite key
     umin[b] = 0xFFFFFFFFu;  // above every finite key
   }
   __syncthreads();
-  const uint64_t e0 = indptr[d], e1 = indptr[d + 1];
-  const uint32_t slot = slots[d];
-  const uint64_t pbit = 1ull << post_bit(slot);
-  const size_t pword = post_word(slot);
-  for (uint64_t e = e0 + lane; e < e1; e += 64) {
-    const uint32_t j = coords[e];
-    const float v = vals[e];
-    if (v == 0.0f) continue;  // not in nz(x)
-    const uint32_t key = ord_key(v);
-    for (uint32_t o = 0; o < h; ++o) {
-      const uint32_t b = ix.bucket[(size_t)o * ix.dim + j];
-      atomicMax(&umax[b], key);
-      atomicMin(&umin[b], key);
+  uint64_t e0 = 0, e1 = 0;
+  uint32_t slot = 0;
+  if (active) {
+    e0 = indptr[d];
+    e1 = indptr[d + 1];
+    slot = slots[d];
+    const uint64_t pbit = 1ull << post_bit(slot);
+    const size_t pword = post_word(slot);
+    for (uint64_t e = e0 + lane; e < e1; e += 64) {
+      const uint32_t j = coords[e];
+      const float v = vals[e];
+      if (v == 0.0f) continue;  // not in nz(x)
+      const uint32_t key = ord_key(v);
+      for (uint32_t o = 0; o < h; ++o) {
+        const uint32_t b = ix.bucket[(size_t)o * ix.dim + j];
+        atomicMax(&umax[b], key);
+        atomicMin(&umin[b], key);
+      }
+      if (postings) atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + pword], (unsigned long long)pbit);
     }
-    atomicOr((unsigned long long *)&ix.bits[(size_t)j * ix.W + pword], (unsigned long long)pbit);
   }
   __syncthreads();
+  if (!active) return;
   const bool bf = (ix.flags & kSketchBf16) != 0, lower = (ix.flags & kUpperOnly) == 0;
   for (uint32_t b = lane; b < m; b += 64) {
     const uint32_t a = umax[b], c = umin[b];
@@ -108,6 +114,18 @@ __global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const ui
     atomicOr((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)(1ull << slot_bit(slot)));
     ix.stale[slot >> 10] = 1u;  // the block's array containers no longer list all its postings
   }
+}
+
+__global__ __launch_bounds__(64) void k_insert(DevIndex ix, uint32_t n, const uint32_t *__restrict__ slots,
+                                               const uint32_t *__restrict__ ids,
+                                               const uint64_t *__restrict__ indptr,
+                                               const uint32_t *__restrict__ coords,
+                                               const float *__restrict__ vals, DevForward fw,
+                                               const uint64_t *__restrict__ doc_off) {
+  extern __shared__ uint32_t ins_lds[];  // 2m words: running max keys, then min keys
+  const uint32_t d = upd_doc(n);
+  if (d >= n) return;
+  insert_doc(ix, true, d, slots, ids, indptr, coords, vals, fw, doc_off, ins_lds, ins_lds + ix.m, true);
 }
 
 hipError_t launch_insert(const DevIndex &ix, uint32_t n, const uint32_t *slots, const uint32_t *ids,

@@ -414,15 +414,18 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
   uint32_t r_id = n;
   snn_status id_st = SNN_OK;
   {
-    std::unordered_map<uint32_t, uint32_t> seen;
-    seen.reserve((size_t)n * 2);
+    IdMap seen;
+    seen.reserve(n);
     for (uint32_t r = 0; r < n && r_id == n; ++r) {
-      if (ids[r] == 0xFFFFFFFFu)
+      if (ids[r] == 0xFFFFFFFFu) {
         id_st = ix->fail(SNN_E_INVALID, "insert: id 0xFFFFFFFF is reserved");
-      else if (ix->id2slot.count(ids[r]))
+      } else if (ix->id2slot.contains(ids[r])) {
         id_st = ix->fail(SNN_E_EXISTS, "insert: id %u is already live", ids[r]);
-      else if (!seen.emplace(ids[r], r).second)
+      } else if (seen.contains(ids[r])) {
         id_st = ix->fail(SNN_E_INVALID, "insert: id %u twice in one batch", ids[r]);
+      } else {
+        seen.put(ids[r], r);
+      }
       if (id_st != SNN_OK) r_id = r;
     }
   }
@@ -498,7 +501,7 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
   ix->id2slot.reserve(ix->id2slot.size() + n);
   for (uint32_t r = 0; r < n; ++r) {
     const uint32_t s = slot_of[r];
-    ix->id2slot[ids[r]] = s;
+    ix->id2slot.put(ids[r], s);
     ix->slot_id[s] = ids[r];
   }
   par_ranges(n, 1024, [&](uint64_t a, uint64_t b) {  // distinct slots: distinct vectors
@@ -519,12 +522,14 @@ extern "C" snn_status snn_delete_batch(snn_index *ix, uint32_t n, const uint32_t
   if (n == 0) return SNN_OK;
   if (!ids) return ix->fail(SNN_E_INVALID, "delete: null ids");
   std::vector<uint32_t> slots(n);
-  std::unordered_map<uint32_t, int> seen;
+  IdMap seen;
+  seen.reserve(n);
   for (uint32_t r = 0; r < n; ++r) {
-    auto it = ix->id2slot.find(ids[r]);
-    if (it == ix->id2slot.end()) return ix->fail(SNN_E_NOT_FOUND, "delete: id %u is not live", ids[r]);
-    if (!seen.emplace(ids[r], 1).second) return ix->fail(SNN_E_INVALID, "delete: id %u twice in one batch", ids[r]);
-    slots[r] = it->second;
+    const uint32_t *it = ix->id2slot.find(ids[r]);
+    if (!it) return ix->fail(SNN_E_NOT_FOUND, "delete: id %u is not live", ids[r]);
+    if (seen.contains(ids[r])) return ix->fail(SNN_E_INVALID, "delete: id %u twice in one batch", ids[r]);
+    seen.put(ids[r], r);
+    slots[r] = *it;
   }
   std::vector<uint64_t> ptr(n + 1, 0);
   std::vector<uint32_t> co;
@@ -1270,9 +1275,9 @@ extern "C" snn_status snn_bucket_table(snn_index *ix, uint32_t *out) {
 
 extern "C" snn_status snn_read_sketch(snn_index *ix, uint32_t id, float *u, float *l) {
   if (!ix || !u || !l) return SNN_E_INVALID;
-  auto it = ix->id2slot.find(id);
-  if (it == ix->id2slot.end()) return ix->fail(SNN_E_NOT_FOUND, "read_sketch: id %u is not live", id);
-  const uint32_t s = it->second;
+  const uint32_t *it = ix->id2slot.find(id);
+  if (!it) return ix->fail(SNN_E_NOT_FOUND, "read_sketch: id %u is not live", id);
+  const uint32_t s = *it;
   HIP_TRY(ix, hipStreamSynchronize(ix->stream), "sync");
   const uint32_t m = ix->cfg.m;
   if (ix->cfg.flags & SNN_SKETCH_BF16) {

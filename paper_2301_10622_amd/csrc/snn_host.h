@@ -72,6 +72,81 @@ struct Tune {
   int qgroup = 1;        // queries per batched workgroup (h = 1)
 };
 
+// External id -> slot: open addressing with linear probing over a power-of-two
+// table (at most half full), erase by backward shift, so no tombstones. The
+// id 0xFFFFFFFF is reserved by the API and marks an empty cell.
+class IdMap {
+ public:
+  static constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+  size_t size() const { return n_; }
+  void reserve(size_t want) {
+    size_t cap = 16;
+    while (cap < 2 * want) cap <<= 1;
+    if (cap > keys_.size()) rehash(cap);
+  }
+  const uint32_t *find(uint32_t id) const {
+    if (keys_.empty()) return nullptr;
+    for (size_t i = slot_of(id);; i = (i + 1) & mask_) {
+      if (keys_[i] == id) return &vals_[i];
+      if (keys_[i] == kEmpty) return nullptr;
+    }
+  }
+  bool contains(uint32_t id) const { return find(id) != nullptr; }
+  // inserts or overwrites
+  void put(uint32_t id, uint32_t slot) {
+    if (2 * (n_ + 1) > keys_.size()) rehash(keys_.empty() ? 16 : 2 * keys_.size());
+    size_t i = slot_of(id);
+    while (keys_[i] != kEmpty && keys_[i] != id) i = (i + 1) & mask_;
+    if (keys_[i] == kEmpty) ++n_;
+    keys_[i] = id;
+    vals_[i] = slot;
+  }
+  // false when absent
+  bool erase(uint32_t id) {
+    if (keys_.empty()) return false;
+    size_t i = slot_of(id);
+    while (keys_[i] != id) {
+      if (keys_[i] == kEmpty) return false;
+      i = (i + 1) & mask_;
+    }
+    // shift later members of the probe run back into the hole
+    for (size_t j = (i + 1) & mask_;; j = (j + 1) & mask_) {
+      if (keys_[j] == kEmpty) break;
+      const size_t home = slot_of(keys_[j]);
+      // j's entry may move to i when its home is not within (i, j] cyclically
+      if (((j - home) & mask_) >= ((j - i) & mask_)) {
+        keys_[i] = keys_[j];
+        vals_[i] = vals_[j];
+        i = j;
+      }
+    }
+    keys_[i] = kEmpty;
+    --n_;
+    return true;
+  }
+  template <typename F>
+  void for_each(F f) const {
+    for (size_t i = 0; i < keys_.size(); ++i)
+      if (keys_[i] != kEmpty) f(keys_[i], vals_[i]);
+  }
+
+ private:
+  size_t slot_of(uint32_t id) const { return (size_t)((id * 0x9E3779B97F4A7C15ull) >> 32) & mask_; }
+  void rehash(size_t cap) {
+    std::vector<uint32_t> ok, ov;
+    ok.swap(keys_);
+    ov.swap(vals_);
+    keys_.assign(cap, kEmpty);
+    vals_.assign(cap, 0);
+    mask_ = cap - 1;
+    n_ = 0;
+    for (size_t i = 0; i < ok.size(); ++i)
+      if (ok[i] != kEmpty) put(ok[i], ov[i]);
+  }
+  std::vector<uint32_t> keys_, vals_;
+  size_t mask_ = 0, n_ = 0;
+};
+
 struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
 
 // Device state of a learned-filter pass: feature table and bf16 weights, per-query
@@ -232,7 +307,7 @@ struct snn_index {
   snn::DevForward fw{};  // forward store (SNN_FORWARD_STORE)
 
   // slot store
-  std::unordered_map<uint32_t, uint32_t> id2slot;
+  snn::IdMap id2slot;
   std::vector<uint32_t> slot_id;             // external id per slot (0xFFFFFFFF = free)
   std::vector<std::vector<uint32_t>> fwd;    // coordinates of the document in each slot
   std::vector<uint32_t> free_slots;          // freed columns, reused first

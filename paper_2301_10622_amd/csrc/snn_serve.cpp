@@ -87,7 +87,7 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
   {
     std::unordered_set<uint32_t> live;
     live.reserve(ix->id2slot.size() * 2 + n);
-    for (auto &kv : ix->id2slot) live.insert(kv.first);
+    ix->id2slot.for_each([&](uint32_t id, uint32_t) { live.insert(id); });
     VecCheck vc;
     vc.stamps = tr->n >= 256 && ix->cfg.dim <= (1u << 20);
     size_t cap_left = ix->free_slots.size() + (ix->cap - ix->next_fresh);
@@ -357,7 +357,7 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
           g_slots.push_back(slot);
           g_ids.push_back(id);
           g_seqs.push_back(r + 1);
-          ix->id2slot[id] = slot;
+          ix->id2slot.put(id, slot);
           ix->slot_id[slot] = id;
           std::vector<uint32_t> &f = ix->fwd[slot];
           f.clear();
@@ -370,7 +370,7 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
           // is the order that matters: a document inserted and deleted in the same
           // round gets its insert sequence first
           const uint32_t id = tr->id[r];
-          const uint32_t slot = ix->id2slot[id];
+          const uint32_t slot = *ix->id2slot.find(id);  // validated live above
           ix->id2slot.erase(id);
           ix->slot_id[slot] = 0xFFFFFFFFu;
           del_slots.push_back(slot);

@@ -45,3 +45,17 @@ def test_live_bits_are_lane_masks_per_group(table):
     # word 4 g + i of group g has bit l set for slot 256 g + 4 l + i: a wavefront lane mask
     g, lane, i = s >> 8, (s >> 2) & 63, s & 3
     assert np.array_equal(w, 4 * g + i) and np.array_equal(b, lane)
+
+
+def test_id_map_against_unordered_map(tmp_path):
+    """The library's open-addressing id -> slot map (snn_host.h), compiled for
+    the host, agrees with std::unordered_map over 400,000 random puts,
+    overwrites and erases with colliding ids."""
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path / "idmap_check")
+    src = os.path.join(ROOT, "tests", "host", "idmap_check.cpp")
+    subprocess.check_call([HIPCC, "-x", "hip", "--offload-arch=gfx950", "-O1", "-I",
+                           os.path.join(ROOT, "paper_2301_10622_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
+                           src, "-o", exe])
+    assert subprocess.check_output([exe]).decode().strip() == "ok"
