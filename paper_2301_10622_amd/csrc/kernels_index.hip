@@ -156,7 +156,10 @@ __global__ __launch_bounds__(64) void k_delete(DevIndex ix, uint32_t n, const ui
   if (clear_bits) {
     for (uint64_t e = indptr[d] + threadIdx.x; e < indptr[d + 1]; e += 64)
       atomicAnd((unsigned long long *)&ix.bits[(size_t)coords[e] * ix.W + pword], (unsigned long long)pmask);
-    if (threadIdx.x == 0) ix.stale[slot >> 10] = 1u;  // its array containers still list the slot
+    // A slot deleted whole keeps its listed array postings: with its live bit
+    // clear its score is never selected, and the insert that reuses it marks
+    // the block stale. Postings cleared from a live slot make it stale now.
+    if (threadIdx.x == 0 && !clear_live) ix.stale[slot >> 10] = 1u;
   }
   if (clear_live && threadIdx.x == 0)
     atomicAnd((unsigned long long *)&ix.live[slot_word(slot)], (unsigned long long)~(1ull << slot_bit(slot)));

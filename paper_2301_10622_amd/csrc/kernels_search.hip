@@ -315,17 +315,39 @@ __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end
       }
     } else {
       // stale block: the same terms from the posting bitmaps; lane l owns
-      // block offsets 256g + 4l + i, at bit 4g + i of its 16-bit chunk
-      for (uint64_t e = e_begin; e < e_end; ++e) {
-        const uint32_t j = qj[e];
-        const float q = qq[e];
-        uint32_t bits = (uint32_t)((const uint16_t *)(ix.bits + (size_t)j * ix.W + ((size_t)blk << 4)))[lane];
-        while (bits) {
-          const uint32_t x = (uint32_t)__builtin_ctz(bits);
-          bits &= bits - 1u;
-          add(e, q, 256u * (x >> 2) + 4u * lane + (x & 3u));
+      // block offsets 256g + 4l + i, at bit 4g + i of its 16-bit chunk. CH
+      // entries at a time: their bits, then the bound of each lane's first
+      // listed slot of every entry, are requested together; the adds go entry
+      // by entry, a lane's further slots of an entry right after its first
+      const uint16_t *bw = (const uint16_t *)(ix.bits + ((size_t)blk << 4)) + lane;  // row j: bw[j * 4W]
+      for (uint64_t e = e_begin; e < e_end; e += CH) {
+        uint32_t bits[CH], o1[CH];
+        float qv[CH], v1[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const bool in = e + k < e_end;
+          const uint64_t ek = in ? e + k : e;
+          qv[k] = qq[ek];
+          bits[k] = in ? (uint32_t)bw[(size_t)qj[ek] * ix.W * 4u] : 0u;
         }
-        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          const uint32_t x = (uint32_t)__builtin_ctz(bits[k] | 0x10000u);
+          o1[k] = bits[k] ? 256u * (x >> 2) + 4u * lane + (x & 3u) : 0xFFFFu;
+          const bool mine = o1[k] >= lo && o1[k] < hi;
+          v1[k] = mine ? gather_bound<kBf16, kH1>(ix, qb, e + k, h, qv[k] > 0.0f, bslot0 + o1[k]) : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+          if (o1[k] >= lo && o1[k] < hi) spb[o1[k] - lo] = __builtin_fmaf(qv[k], v1[k], spb[o1[k] - lo]);
+          uint32_t rest = bits[k] & (bits[k] - 1u);
+          while (rest) {
+            const uint32_t x = (uint32_t)__builtin_ctz(rest);
+            rest &= rest - 1u;
+            add(e + k, qv[k], 256u * (x >> 2) + 4u * lane + (x & 3u));
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
       }
     }
   }

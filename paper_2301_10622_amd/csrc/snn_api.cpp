@@ -205,6 +205,7 @@ extern "C" snn_status snn_create(const snn_config *cfg, void *hip_stream, snn_in
   ix->cfg = *cfg;
   ix->cap = (uint32_t)(((uint64_t)cfg->capacity + kTileMax - 1) / kTileMax * kTileMax);
   ix->W = ix->cap / 64;
+  ix->free_slots.init(ix->cap);
   ix->stream = (hipStream_t)hip_stream;
   if (hipGetDevice(&ix->device) != hipSuccess) {
     delete ix;
@@ -477,17 +478,10 @@ extern "C" snn_status snn_insert_batch(snn_index *ix, uint32_t n, const uint32_t
         }
     }
   });
-  // assign slots: reuse freed columns first (Section 4.3), then fresh ones
+  // assign slots: freed columns (Section 4.3) and fresh ones, in the pool's order
   std::vector<uint32_t> slot_of(n);
   std::vector<uint32_t> vid(ids, ids + n);
-  for (uint32_t r = 0; r < n; ++r) {
-    if (!ix->free_slots.empty()) {
-      slot_of[r] = ix->free_slots.back();
-      ix->free_slots.pop_back();
-    } else {
-      slot_of[r] = ix->next_fresh++;
-    }
-  }
+  for (uint32_t r = 0; r < n; ++r) slot_of[r] = ix->free_slots.take(ix->next_fresh, ix->cap, ix->array_coords > 0);
   // upload in chunks of at most ~16M entries
   const size_t kChunk = (size_t)16 << 20;
   size_t r0 = 0;
@@ -546,7 +540,7 @@ extern "C" snn_status snn_delete_batch(snn_index *ix, uint32_t n, const uint32_t
     ix->slot_id[s] = 0xFFFFFFFFu;
     ix->fwd[s].clear();
     ix->fwd[s].shrink_to_fit();
-    ix->free_slots.push_back(s);
+    ix->free_slots.release(s);
   }
   ix->live -= n;
   ix->mutations++;

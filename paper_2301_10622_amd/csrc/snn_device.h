@@ -25,9 +25,11 @@
 //                                 entry closes it)
 //   post     uint16 [entries]     the posting slots of array rows, as offsets inside
 //                                 their block, in any order within a segment
-//   stale    uint32 [nblk]        non-zero for a block whose postings changed since
-//                                 the last compaction (its array segments are out of
-//                                 date; the bitmaps never are)
+//   stale    uint32 [nblk]        non-zero for a block with a slot inserted (or a live
+//                                 slot's postings cleared) since the last compaction:
+//                                 its array segments are out of date, the bitmaps
+//                                 never are (a slot deleted whole keeps its listed
+//                                 postings; it is not live, so its score is unused)
 //
 // Containers (the id lists of Section 4.1, Notes on Implementation, held the
 // way Roaring holds them): every coordinate keeps its posting bitmap, which

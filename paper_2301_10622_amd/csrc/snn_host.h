@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <set>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -145,6 +147,87 @@ class IdMap {
   }
   std::vector<uint32_t> keys_, vals_;
   size_t mask_ = 0, n_ = 0;
+};
+
+// Free slots, grouped by 1,024-slot block, and the order in which inserts take
+// them. Every insert marks its block stale (until the next compaction the
+// block's array-container coordinates are read from the posting bitmaps), and
+// a mirror of those marks is kept here. Before any compaction has built array
+// containers, freed slots are reused first and fresh ones taken after them
+// (Section 4.3). Once array containers exist, an insert goes where it costs
+// least: a free slot of a block already stale, then a fresh slot (the tail
+// blocks), and only then a free slot of a clean block -- the one with the most
+// free slots, which then counts as stale for the slots after it.
+class SlotPool {
+ public:
+  void init(uint32_t cap) {
+    nblk_ = cap >> 10;
+    free_.assign(nblk_, {});
+    stale_.assign(nblk_, 0);
+    stale_free_.clear();
+    clean_.clear();
+    count_ = 0;
+  }
+  size_t size() const { return count_; }
+  bool is_stale(uint32_t blk) const { return stale_[blk] != 0; }
+
+  void release(uint32_t slot) {
+    const uint32_t b = slot >> 10;
+    auto &f = free_[b];
+    if (stale_[b]) {
+      if (f.empty()) stale_free_.insert(b);
+    } else {
+      if (!f.empty()) clean_.erase({(uint32_t)f.size(), b});
+      clean_.insert({(uint32_t)f.size() + 1, b});
+    }
+    f.push_back(slot);
+    ++count_;
+  }
+
+  // The slot of the next insert; the caller has checked that one is left
+  // (size() > 0 or next_fresh < cap). arrays: array containers exist.
+  uint32_t take(uint32_t &next_fresh, uint32_t cap, bool arrays) {
+    if (!stale_free_.empty()) return pop(*stale_free_.begin());
+    if ((arrays || clean_.empty()) && next_fresh < cap) {
+      const uint32_t s = next_fresh++;
+      mark_stale(s >> 10);
+      return s;
+    }
+    const uint32_t b = clean_.rbegin()->second;
+    mark_stale(b);
+    return pop(b);
+  }
+
+  // after a compaction: no block is stale
+  void clear_stale() {
+    for (uint32_t b : stale_free_) clean_.insert({(uint32_t)free_[b].size(), b});
+    stale_free_.clear();
+    std::fill(stale_.begin(), stale_.end(), (uint8_t)0);
+  }
+
+ private:
+  void mark_stale(uint32_t b) {
+    if (stale_[b]) return;
+    stale_[b] = 1;
+    if (!free_[b].empty()) {
+      clean_.erase({(uint32_t)free_[b].size(), b});
+      stale_free_.insert(b);
+    }
+  }
+  uint32_t pop(uint32_t b) {  // b is stale with free slots
+    auto &f = free_[b];
+    const uint32_t s = f.back();
+    f.pop_back();
+    if (f.empty()) stale_free_.erase(b);
+    --count_;
+    return s;
+  }
+  uint32_t nblk_ = 0;
+  std::vector<std::vector<uint32_t>> free_;
+  std::vector<uint8_t> stale_;
+  std::set<uint32_t> stale_free_;                       // stale blocks with free slots
+  std::set<std::pair<uint32_t, uint32_t>> clean_;       // (free slots, block) of clean blocks
+  size_t count_ = 0;
 };
 
 struct LearnedFilter;   // learned k-th-score pre-filter (kernels_mlp.hip)
@@ -310,7 +393,7 @@ struct snn_index {
   snn::IdMap id2slot;
   std::vector<uint32_t> slot_id;             // external id per slot (0xFFFFFFFF = free)
   std::vector<std::vector<uint32_t>> fwd;    // coordinates of the document in each slot
-  std::vector<uint32_t> free_slots;          // freed columns, reused first
+  snn::SlotPool free_slots;                  // freed columns and the order inserts take them
   // forward store (SNN_FORWARD_STORE): device entries dev.fwd[0 .. fwd_cap), of
   // which [0, fwd_top) have been handed out. Each slot owns a region of a
   // power-of-two size; a region too small for a new document goes to the free
@@ -330,6 +413,7 @@ struct snn_index {
   std::vector<uint8_t> classes;
   uint32_t list_rows = 0;
   uint64_t list_postings = 0;
+  uint32_t array_coords = 0;  // coordinates of class 1
 
   // buffers
   snn::DevBuf up;

@@ -125,6 +125,8 @@ snn_status snn_index::compact(const uint8_t *pinned) {
   dev.seg = (const uint32_t *)lists_seg.p;
   dev.post = (const uint16_t *)lists_post.p;
   classes = cls;
+  array_coords = (uint32_t)std::count(cls.begin(), cls.end(), (uint8_t)1);
+  free_slots.clear_stale();
   list_rows = nrows;
   list_postings = total;
   graphs.clear();  // captured launches hold the old containers

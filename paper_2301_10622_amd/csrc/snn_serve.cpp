@@ -306,7 +306,7 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
                           M),
             "serve reclaim");
     HIP_TRY(ix, hipFreeAsync(dp, M), "serve upload");
-    for (uint32_t s : sl) ix->free_slots.push_back(s);
+    for (uint32_t s : sl) ix->free_slots.release(s);
     return SNN_OK;
   };
 
@@ -346,13 +346,7 @@ extern "C" snn_status snn_serve_run(snn_index *ix, const snn_trace *tr, const sn
         // mutations apply in order; a pending run of inserts is flushed before a delete
         if (kd == 1) {
           if (g_slots.empty()) first_ins = ins_index[r];
-          uint32_t slot;
-          if (!ix->free_slots.empty()) {
-            slot = ix->free_slots.back();
-            ix->free_slots.pop_back();
-          } else {
-            slot = ix->next_fresh++;
-          }
+          const uint32_t slot = ix->free_slots.take(ix->next_fresh, ix->cap, ix->array_coords > 0);
           const uint32_t id = tr->id[r];
           g_slots.push_back(slot);
           g_ids.push_back(id);

@@ -1,7 +1,7 @@
 """Array containers (the sparse-list form of Section 4.1, Notes on
 Implementation) next to the posting bitmaps: the classes a compaction picks,
-results against the FP64 oracle in every schedule, stale blocks (changed after
-the compaction, read from the bitmaps) against a fresh compaction with the same
+results against the FP64 oracle in every schedule, slots changed after the
+compaction (read from the bitmaps) against a fresh compaction with the same
 classes, and segments longer than one wave step."""
 import numpy as np
 import pytest
@@ -111,14 +111,17 @@ def test_arrays_match_the_oracle_in_every_schedule(multi, k):
 
 def test_stale_blocks_give_the_bits_of_a_fresh_compaction():
     """Deletes, inserts into freed and fresh slots and re-inserts after the
-    compaction mark their blocks stale; searches read those blocks from the
-    bitmaps and give exactly the bits of the same index compacted again with
-    the same classes (every block read from arrays), in every schedule; and
-    the oracle's top-k of the live set."""
+    compaction: the inserted slots are marked changed and read from the
+    bitmaps, the deleted ones keep their listed postings; searches give
+    exactly the bits of the same index compacted again with the same classes
+    (every slot read from arrays), in every schedule; and the oracle's top-k
+    of the live set."""
     P = _lib()
-    w = gen.make_small(7, docs=40_000, queries=30)
+    # 47,152 documents in 49,152 slots: the first inserts take the 2,000 fresh
+    # slots, the rest reuse freed ones (whose listed postings are stale)
+    w = gen.make_small(7, docs=47_152, queries=30)
     pool = gen.small_docs(8, 20_000)
-    ix = P.Index(w.n, w.m, w.h, capacity=60_000, hash_seed=w.hash_seed)
+    ix = P.Index(w.n, w.m, w.h, capacity=w.docs.rows, hash_seed=w.hash_seed)
     P.load_docs(ix, w.docs)
     cls = ix.container_classes()
     rng = np.random.default_rng(9)
@@ -126,13 +129,13 @@ def test_stale_blocks_give_the_bits_of_a_fresh_compaction():
     nxt = 0
     t = _dev(w.queries)
     for step, k in enumerate((10, 100)):
-        # deletes, then inserts that take the freed slots first and then fresh
-        # ones, then re-inserts of deleted ids with new vectors
-        dels = rng.choice(sorted(live), 1500, replace=False).astype(np.uint32)
+        # deletes, then inserts (fresh slots while any are left, then freed
+        # ones), then re-inserts of deleted ids with new vectors
+        dels = rng.choice(sorted(live), 3000, replace=False).astype(np.uint32)
         ix.delete_batch(dels)
         for d in dels:
             del live[int(d)]
-        for ids in (np.arange(4000, dtype=np.uint32) + 100_000 + 10_000 * step, dels[:300]):
+        for ids in (np.arange(2500, dtype=np.uint32) + 100_000 + 10_000 * step, dels[:300]):
             sub = pool.take(range(nxt, nxt + len(ids)))
             ix.insert_batch(ids, sub.indptr, sub.coords, sub.vals)
             for i, r in zip(ids, range(nxt, nxt + len(ids))):

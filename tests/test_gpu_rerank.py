@@ -116,7 +116,8 @@ def test_rerank_after_deletes_and_reinserts():
     pool = gen.sparse_rows(41, 12000, 1000, 1.1, rng.integers(5, 120, 12000), "normal")
     qs = gen.sparse_rows(42, 40, 1000, 1.1, rng.integers(5, 60, 40), "normal")
     ix = P.Index(1000, 32, 2, capacity=8000, hash_seed=7, forward_store=True)
-    P.load_docs(ix, pool.take(range(n)))
+    # no array containers: inserts then reuse freed slots before fresh ones
+    P.load_docs(ix, pool.take(range(n)), compact=False)
     live = {i: i for i in range(n)}
     nxt = n
     for step in range(4):

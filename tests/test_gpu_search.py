@@ -223,10 +223,11 @@ def test_streaming_history_equals_fresh_index():
     rng = np.random.default_rng(5)
     pool = gen.sparse_rows(31, 30000, 1000, 1.1, rng.integers(20, 61, 30000), "normal")
     qs = gen.sparse_rows(32, 20, 1000, 1.1, np.full(20, 20), "normal")
-    ix = _fresh(1000, 32, 1, 20000, seed=4)
+    ix = _fresh(1000, 32, 1, 16384, seed=4)
     live = {}
     next_doc = 0
-    # bulk load 12k, then a random history of deletes and inserts
+    # bulk load 12k, then a random history of deletes and inserts (the 4,384
+    # fresh slots run out in the second step; later inserts reuse freed slots)
     P.load_docs(ix, pool.take(range(12000)), ids=np.arange(12000, dtype=np.uint32) * 3 + 1)
     for i in range(12000):
         live[i * 3 + 1] = i
@@ -509,12 +510,12 @@ def test_sampled_thresholds_graph_replays_follow_the_live_count():
     import torch
 
     P = _lib()
-    w = gen.make_small(6, docs=270_000, queries=8)
+    w = gen.make_small(6, docs=278_528, queries=8)  # every slot used: inserts reuse freed ones
     stream = torch.cuda.Stream()  # a capturable (non-default) stream, default priority
     torch.cuda.set_stream(stream)
-    ix = P.Index(w.n, w.m, w.h, capacity=270_000, hash_seed=w.hash_seed, stream=stream)
+    ix = P.Index(w.n, w.m, w.h, capacity=278_528, hash_seed=w.hash_seed, stream=stream)
     P.load_docs(ix, w.docs)
-    ix.delete_batch(np.arange(3000, 270_000))
+    ix.delete_batch(np.arange(3000, 278_528))
     t = _dev_batch(w.queries)
     dev = torch.device("cuda:0")
     k = 4000
