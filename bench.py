@@ -121,8 +121,15 @@ def main():
         ix.compact()
         t_compact = time.time() - t
         cls = ix.container_classes()
+        ll = np.bincount(w.docs.coords, minlength=w.n).astype(np.int64)
+        nap = int(ll[cls != 0].sum())
+        nrows = int(np.count_nonzero((cls != 0) & (ll > 0)))
+        nblk = -(-w.docs.rows // 16384) * 16
+        # offsets (2 bytes) and both bounds (4 bytes each) per array posting, and the block-offset rows
+        cbytes = nap * (2 + 4 + 4) + (nrows + 1) * (nblk + 1) * 4
         containers.update({"compaction_s": round(t_compact, 4), "array_coords": int(cls.sum()), "dim": w.n,
-                           "query_entries_with_arrays": round(float(cls[w.queries.coords].mean()), 4)})
+                           "query_entries_with_arrays": round(float(cls[w.queries.coords].mean()), 4),
+                           "array_postings": nap, "all_postings": int(ll.sum()), "container_bytes": cbytes})
         log("compaction %.3fs: %d of %d coordinates with array containers" % (t_compact, int(cls.sum()), w.n))
     ix.profile(False)
     log("index built: %.2fs (%.0f docs/s through the host API; insert kernel %.2f ms for %d docs)" % (
@@ -628,17 +635,22 @@ def measured_counters(kernel, k):
 
 def compulsory_bytes(np, w, classes, list_len, buckets, sketch_bytes=4):
     """HBM bytes a batch of the workload must read at least once: the posting
-    containers of every distinct query coordinate (a bitmap over the used slots,
-    or an array container: 2 bytes per posting plus its row of block offsets),
-    every sketch row (bucket, U or L half) a query entry touches, over the used
-    slots, the live bitmap, and 16 bytes per prepared query entry."""
+    containers of every distinct query coordinate (a bitmap over the used
+    slots, or an array container: its row of block offsets, 2 bytes per
+    posting, and per sign the coordinate is queried with the stored bound of
+    each posting), every sketch row (bucket, U or L half) a query entry of a
+    bitmap coordinate touches, over the used slots, the live bitmap, and 16
+    bytes per prepared query entry."""
     used = -(-w.docs.rows // 1024) * 1024
     qc = w.queries.coords.astype(np.int64)
+    neg = (w.queries.vals < 0).astype(np.int64)
     j = np.unique(qc)
     arr = classes[j] != 0
     cont = float(np.sum(np.where(arr, 2 * list_len[j] + (used // 1024 + 1) * 4, used // 8)))
-    neg = (w.queries.vals < 0).astype(np.int64)
-    rows = np.unique(np.concatenate([buckets[o][qc].astype(np.int64) * 2 + neg for o in range(len(buckets))]))
+    signed = np.unique(qc * 2 + neg) // 2  # one per (coordinate, sign) queried
+    cont += float(np.sum(np.where(classes[signed] != 0, sketch_bytes * list_len[signed], 0)))
+    bm = classes[qc] == 0
+    rows = np.unique(np.concatenate([buckets[o][qc[bm]].astype(np.int64) * 2 + neg[bm] for o in range(len(buckets))]))
     return cont + float(len(rows)) * used * sketch_bytes + used / 8 + 16.0 * len(qc)
 
 

@@ -204,10 +204,15 @@ constexpr uint32_t kListChunk = 2048;  // blocks per pass of k_build_lists (8 pe
 // One workgroup per array row r (coordinate row_coord[r]): segment starts
 // seg[r][b] = rbase[r] + postings of the row in blocks before b, and
 // seg[r][nblk] = rbase[r] + the row's count; the postings of block b go to
-// post[seg[r][b] ..] as block offsets, lane l's set bits in bit order.
+// post[seg[r][b] ..] as block offsets, lane l's set bits in bit order, and
+// the bounds of each posting to pu / pl at the same place: the sketch's
+// bounds for coordinate j at the slot (Alg. 6), the smallest of its h upper
+// entries and the largest of its h lower entries, folded in mapping order
+// with fminf / fmaxf as the scoring kernels fold them.
 __global__ __launch_bounds__(256) void k_build_lists(DevIndex ix, const uint32_t *__restrict__ row_coord,
                                                      const uint64_t *__restrict__ rbase, uint32_t *__restrict__ seg,
-                                                     uint16_t *__restrict__ post) {
+                                                     uint16_t *__restrict__ post, void *__restrict__ pu,
+                                                     void *__restrict__ pl) {
   __shared__ uint32_t cb[kListChunk];
   __shared__ uint32_t wsum[4];
   const uint32_t r = blockIdx.x;
@@ -216,6 +221,7 @@ __global__ __launch_bounds__(256) void k_build_lists(DevIndex ix, const uint32_t
   const uint64_t *row = ix.bits + (size_t)j * ix.W;
   uint32_t *sr = seg + (size_t)r * (nblk + 1);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool bf = (ix.flags & kSketchBf16) != 0, lower = (ix.flags & kUpperOnly) == 0;
   uint64_t carry = rbase[r];
   for (uint32_t b0 = 0; b0 < nblk; b0 += kListChunk) {
     const uint32_t nb = min(kListChunk, nblk - b0);
@@ -268,7 +274,27 @@ __global__ __launch_bounds__(256) void k_build_lists(DevIndex ix, const uint32_t
       while (b) {
         const uint32_t x = (uint32_t)__builtin_ctz(b);
         b &= b - 1u;
-        post[at++] = (uint16_t)(256u * (x >> 2) + 4u * (uint32_t)lane + (x & 3u));
+        const uint32_t off = 256u * (x >> 2) + 4u * (uint32_t)lane + (x & 3u);
+        const size_t slot = ((size_t)(b0 + i) << 10) + off;
+        post[at] = (uint16_t)off;
+        float u = 0.0f, l = 0.0f;
+        for (uint32_t o = 0; o < ix.h; ++o) {
+          const size_t a = (size_t)ix.bucket[(size_t)o * ix.dim + j] * ix.cap + slot;
+          const float uo = bf ? __builtin_bit_cast(float, (uint32_t)((const uint16_t *)ix.U)[a] << 16) : ix.U[a];
+          u = o ? __builtin_fminf(u, uo) : uo;
+          if (lower) {
+            const float lo = bf ? __builtin_bit_cast(float, (uint32_t)((const uint16_t *)ix.L)[a] << 16) : ix.L[a];
+            l = o ? __builtin_fmaxf(l, lo) : lo;
+          }
+        }
+        if (bf) {
+          ((uint16_t *)pu)[at] = (uint16_t)(__builtin_bit_cast(uint32_t, u) >> 16);
+          if (lower) ((uint16_t *)pl)[at] = (uint16_t)(__builtin_bit_cast(uint32_t, l) >> 16);
+        } else {
+          ((float *)pu)[at] = u;
+          if (lower) ((float *)pl)[at] = l;
+        }
+        ++at;
       }
     }
     carry += chunk_total;
@@ -278,9 +304,9 @@ __global__ __launch_bounds__(256) void k_build_lists(DevIndex ix, const uint32_t
 }
 
 hipError_t launch_build_lists(const DevIndex &ix, uint32_t nrows, const uint32_t *row_coord, const uint64_t *rbase,
-                              uint32_t *seg, uint16_t *post, hipStream_t s) {
+                              uint32_t *seg, uint16_t *post, void *pu, void *pl, hipStream_t s) {
   if (nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_lists, dim3(nrows), dim3(256), 0, s, ix, row_coord, rbase, seg, post);
+  hipLaunchKernelGGL(k_build_lists, dim3(nrows), dim3(256), 0, s, ix, row_coord, rbase, seg, post, pu, pl);
   return hipGetLastError();
 }
 

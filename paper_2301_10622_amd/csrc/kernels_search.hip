@@ -237,10 +237,16 @@ __device__ __forceinline__ float gather_bound(const DevIndex &ix, cptr<uint32_t>
 // the sums of the terms of entries [e_begin, e_end).
 //
 // The segment bounds of up to 64 entries in the block are read at once, lane t
-// holding entry t's (one vector load each, no scalar round trip per entry);
-// then CH entries at a time, the wave requests every offset and every bound of
-// the CH segments before the first add, so CH entries share one pair of memory
-// round trips, and adds them entry by entry.
+// holding entry t's (one vector load each). Their postings, entry after entry,
+// form one list of `total` postings, which the wave takes 64 at a time: lane l
+// takes posting p0 + l, finds its entry by a binary search over the lanes'
+// exclusive prefix sums of the segment lengths, and loads the offset and the
+// posting's bound, which the compaction stored beside it (so no sketch row is
+// gathered from). A wave step thus serves several short segments with
+// contiguous loads. The adds of a step then go entry by entry (one round per
+// distinct entry among its lanes), so each score takes its terms in entry
+// order. A stale block gathers the bounds from the sketch instead; for a slot
+// unchanged since the compaction they are the stored values.
 template <int R, bool kBf16, bool kH1>
 __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end, uint32_t wslot0, float *sp) {
   constexpr int G = R / 4;
@@ -274,41 +280,73 @@ __device__ void score_arrays(const TileArgs &a, uint64_t e_begin, uint64_t e_end
     if (as_const(ix.stale)[blk] == 0u) {
       for (uint64_t eb = e_begin; eb < e_end; eb += 64) {
         const uint32_t ne = (uint32_t)min((uint64_t)64, e_end - eb);
-        uint32_t vs0 = 0, vn = 0;  // lane t: entry eb + t's segment start and length
+        // lane t: entry eb + t's segment start, length and value
+        uint32_t vs0 = 0, vn = 0;
+        float vq = 0.0f;
         if (lane < ne) {
           const size_t rb = (size_t)a.qd.cr[eb + lane] * nblk1 + blk;
           vs0 = ix.seg[rb];
           vn = ix.seg[rb + 1] - vs0;
+          vq = qq[eb + lane];
         }
-        for (uint32_t c0 = 0; c0 < ne; c0 += CH) {
-          uint32_t s0[CH], n[CH], off[CH];
-          float qv[CH], v[CH];
+        // exclusive prefix sum of the lengths over the lanes, and the total
+        uint32_t incl = vn;
 #pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            const bool in = c0 + k < ne;
-            const uint32_t t = in ? c0 + (uint32_t)k : 0u;
-            s0[k] = __builtin_amdgcn_readlane(vs0, t);
-            n[k] = in ? __builtin_amdgcn_readlane(vn, t) : 0u;
-            qv[k] = qq[eb + t];
-            off[k] = lane < n[k] ? (uint32_t)ix.post[s0[k] + lane] : 0xFFFFu;
+        for (int d = 1; d < 64; d <<= 1) {
+          const uint32_t y = __shfl_up(incl, d, 64);
+          if ((int)lane >= d) incl += y;
+        }
+        const uint32_t excl = incl - vn;
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        // S wave steps at a time: their searches, offset and bound loads are
+        // all issued before the first add, so the steps share their latencies
+        constexpr int S = R >= 32 ? 4 : 3;  // 4 where the wave spans several blocks
+        for (uint32_t p0 = 0; p0 < total; p0 += 64u * S) {
+          uint32_t t[S], o[S];
+          float q[S], v[S];
+#pragma unroll
+          for (int k = 0; k < S; ++k) t[k] = 0;
+          // entry of posting p: the last lane u with excl(u) <= p (a lane with
+          // an empty segment shares the next lane's excl, so u's segment is
+          // not empty when p < total)
+#pragma unroll
+          for (uint32_t d = 32; d >= 1; d >>= 1) {
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+              const uint32_t ex = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((t[k] + d) << 2), (int)excl);
+              if (ex <= p0 + 64u * k + lane) t[k] += d;
+            }
           }
 #pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            const bool mine = off[k] >= lo && off[k] < hi;
-            v[k] = mine ? gather_bound<kBf16, kH1>(ix, qb, eb + c0 + k, h, qv[k] > 0.0f, bslot0 + off[k]) : 0.0f;
+          for (int k = 0; k < S; ++k) {
+            const uint32_t p = p0 + 64u * k + lane;
+            const uint32_t s0t = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(t[k] << 2), (int)vs0);
+            const uint32_t ext = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(t[k] << 2), (int)excl);
+            q[k] = __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((int)(t[k] << 2), __builtin_bit_cast(int, vq)));
+            const uint32_t at = s0t + (p - ext);
+            o[k] = 0xFFFFu;
+            v[k] = 0.0f;
+            if (p < total) {
+              o[k] = (uint32_t)ix.post[at];
+              // the posting's bound, stored beside it: U's side for q > 0, L's for q < 0
+              const void *src = q[k] > 0.0f ? ix.pu : ix.pl;
+              if constexpr (kBf16)
+                v[k] = __builtin_bit_cast(float, (uint32_t)((const uint16_t *)src)[at] << 16);
+              else
+                v[k] = ((const float *)src)[at];
+            }
           }
+          // adds, one entry per round, in entry order
 #pragma unroll
-          for (int k = 0; k < CH; ++k) {
-            if (n[k] == 0u) continue;
-            if (off[k] >= lo && off[k] < hi) spb[off[k] - lo] = __builtin_fmaf(qv[k], v[k], spb[off[k] - lo]);
-            __builtin_amdgcn_wave_barrier();
-            // the rest of a segment longer than one wave step (rare: the class
-            // is chosen for at most 64 postings per block on average), before
-            // the next entry's adds
-            for (uint32_t p0 = 64; p0 < n[k]; p0 += 64) {
-              const uint32_t o = p0 + lane < n[k] ? (uint32_t)ix.post[s0[k] + p0 + lane] : 0xFFFFu;
-              add(eb + c0 + k, qv[k], o);
+          for (int k = 0; k < S; ++k) {
+            const bool mine = o[k] >= lo && o[k] < hi;
+            uint64_t rem = __builtin_amdgcn_ballot_w64(mine);
+            while (rem) {
+              const uint32_t tf = __builtin_amdgcn_readlane(t[k], (uint32_t)__builtin_ctzll(rem));
+              const uint64_t grp = __builtin_amdgcn_ballot_w64(t[k] == tf) & rem;
+              if (mine && t[k] == tf) spb[o[k] - lo] = __builtin_fmaf(q[k], v[k], spb[o[k] - lo]);
               __builtin_amdgcn_wave_barrier();
+              rem &= ~grp;
             }
           }
         }

@@ -289,6 +289,8 @@ extern "C" void snn_destroy(snn_index *ix) {
   if (d.stale) (void)hipFree(d.stale);
   ix->lists_seg.release();
   ix->lists_post.release();
+  ix->lists_pu.release();
+  ix->lists_pl.release();
   ix->crow.release();
   if (ix->fw.ent) (void)hipFree(ix->fw.ent);
   if (ix->fw.off) (void)hipFree(ix->fw.off);

@@ -25,6 +25,10 @@
 //                                 entry closes it)
 //   post     uint16 [entries]     the posting slots of array rows, as offsets inside
 //                                 their block, in any order within a segment
+//   pu, pl   float  [entries]     per array posting (coordinate j, slot s), the bounds
+//                                 the sketch gives: min_o U[pi_o(j)][s] and
+//                                 max_o L[pi_o(j)][s] (bfloat16 with SNN_SKETCH_BF16,
+//                                 no pl with SNN_UPPER_ONLY), copied at the compaction
 //   stale    uint32 [nblk]        non-zero for a block with a slot inserted (or a live
 //                                 slot's postings cleared) since the last compaction:
 //                                 its array segments are out of date, the bitmaps
@@ -73,6 +77,7 @@ struct DevIndex {
   uint32_t *stale;       // [nblk] blocks changed since the last compaction
   const uint32_t *seg;   // [rows][nblk + 1] array containers (null before any compaction)
   const uint16_t *post;
+  const void *pu, *pl;   // [entries] bounds of the array postings (float, or bfloat16 bits)
   uint32_t dim, m, h, cap, W;
   uint32_t flags;     // kSketchBf16 | kUpperOnly
 };
@@ -194,7 +199,7 @@ hipError_t launch_prep(const DevIndex &ix, QueryDesc qd, uint32_t nq, const uint
 // the coordinates with a row (crow[j] != kNoRow, rows in rbase order)
 hipError_t launch_count_rows(const DevIndex &ix, uint32_t *cnt, hipStream_t s);
 hipError_t launch_build_lists(const DevIndex &ix, uint32_t nrows, const uint32_t *row_coord, const uint64_t *rbase,
-                              uint32_t *seg, uint16_t *post, hipStream_t s);
+                              uint32_t *seg, uint16_t *post, void *pu, void *pl, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, size_t n, hipStream_t s);
 hipError_t launch_tiles(const TileArgs &a, int R, uint32_t nq_launch, hipStream_t s);

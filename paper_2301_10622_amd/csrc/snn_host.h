@@ -409,7 +409,7 @@ struct snn_index {
 
   // array containers (snn_compact): crow [dim] (null before the first
   // compaction), seg and post; the class of every coordinate (1: array)
-  snn::DevBuf crow, lists_seg, lists_post;
+  snn::DevBuf crow, lists_seg, lists_post, lists_pu, lists_pl;
   std::vector<uint8_t> classes;
   uint32_t list_rows = 0;
   uint64_t list_postings = 0;

@@ -84,20 +84,26 @@ snn_status snn_index::compact(const uint8_t *pinned) {
   const size_t seg_bytes = (size_t)(nrows + 1) * (nblk + 1) * 4;
   // new buffers before the old ones go (a failure leaves the index as it was)
   struct Fresh {
-    DevBuf seg, post, crow, aux;
+    DevBuf seg, post, pu, pl, crow, aux;
     bool keep = false;
     ~Fresh() {
       aux.release();
       if (!keep) {
         seg.release();
         post.release();
+        pu.release();
+        pl.release();
         crow.release();
       }
     }
   } f;
-  DevBuf &seg_n = f.seg, &post_n = f.post, &crow_n = f.crow, &aux = f.aux;
+  DevBuf &seg_n = f.seg, &post_n = f.post, &pu_n = f.pu, &pl_n = f.pl, &crow_n = f.crow, &aux = f.aux;
+  const size_t vbytes = (dev.flags & kSketchBf16) ? 2 : 4;  // one bound, as the sketch holds it
+  const bool lower = (dev.flags & kUpperOnly) == 0;
   HIP_TRY(this, seg_n.ensure(seg_bytes, stream), "array container offsets");
   HIP_TRY(this, post_n.ensure(total * 2 + 64, stream), "array containers");
+  HIP_TRY(this, pu_n.ensure(total * vbytes + 64, stream), "array container bounds");
+  if (lower) HIP_TRY(this, pl_n.ensure(total * vbytes + 64, stream), "array container bounds");
   HIP_TRY(this, crow_n.ensure((size_t)dim * 4, stream), "container rows");
   HIP_TRY(this, aux.ensure((size_t)nrows * 12 + 64, stream), "compaction rows");
   uint32_t *rc_d = (uint32_t *)aux.p;
@@ -111,19 +117,26 @@ snn_status snn_index::compact(const uint8_t *pinned) {
   }
   HIP_TRY(this, launch_fill_u32((uint32_t *)seg_n.p, 0u, nblk + 1, stream), "empty row");
   HIP_TRY(this,
-          launch_build_lists(dev, nrows, rc_d, rb_d, (uint32_t *)seg_n.p + (nblk + 1), (uint16_t *)post_n.p, stream),
+          launch_build_lists(dev, nrows, rc_d, rb_d, (uint32_t *)seg_n.p + (nblk + 1), (uint16_t *)post_n.p, pu_n.p,
+                             pl_n.p, stream),
           "list kernel");
   HIP_TRY(this, launch_fill_u32(dev.stale, 0u, nblk, stream), "stale flags");
   HIP_TRY(this, hipStreamSynchronize(stream), "sync");
   f.keep = true;
   lists_seg.release();
   lists_post.release();
+  lists_pu.release();
+  lists_pl.release();
   crow.release();
   lists_seg = seg_n;
   lists_post = post_n;
+  lists_pu = pu_n;
+  lists_pl = pl_n;
   crow = crow_n;
   dev.seg = (const uint32_t *)lists_seg.p;
   dev.post = (const uint16_t *)lists_post.p;
+  dev.pu = lists_pu.p;
+  dev.pl = lists_pl.p;
   classes = cls;
   array_coords = (uint32_t)std::count(cls.begin(), cls.end(), (uint8_t)1);
   free_slots.clear_stale();
