@@ -654,6 +654,20 @@ def compulsory_bytes(np, w, classes, list_len, buckets, sketch_bytes=4):
     return cont + float(len(rows)) * used * sketch_bytes + used / 8 + 16.0 * len(qc)
 
 
+def oracle_qps(ora, queries, k, threads, reps=3):
+    """The FP64 oracle's search rate (Alg. 6 + FindLargest) on `queries`:
+    median of `reps` runs on `threads` host threads."""
+    import numpy as np
+
+    runs = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        ora.search(queries, k, threads=threads)
+        runs.append(time.perf_counter() - t)
+    return {"qps": round(queries.rows / float(np.median(runs)), 2), "queries": int(queries.rows), "k": k,
+            "threads": threads, "runs_s": [round(x, 3) for x in runs]}
+
+
 def recall_vs_exact(ora, queries, ids, cnt, k, threads):
     """Mean recall@k of the GPU results (ids, counts: numpy rows of `queries`)
     against the oracle's exact brute-force top-k (Eq. 2)."""
@@ -716,6 +730,11 @@ def batch_4m(args, dev, P, gen, np, torch):
         res[name]["recall_at_100"] = rec
     res["recall_sample"] = "%d seeded queries of the batch" % S
     log("batch4m recall@100 %.4f (%d queries)" % (rec, S))
+    if not args.no_cpu_baseline:
+        sub = w.queries.take(np.sort(np.random.default_rng(6).choice(nq, 512, replace=False)))
+        res["cpu_oracle"] = oracle_qps(ora, sub, k, O.max_threads())
+        res["cpu_oracle"]["sample"] = "512 seeded queries of the batch"
+        log("batch4m oracle %.1f q/s (512 queries)" % res["cpu_oracle"]["qps"])
     del ora
     return res
 
@@ -853,6 +872,10 @@ def serving_8m(args, dev, P, gen, np, torch):
         g_ids, _, g_cnt = ix.search_batch(rq.indptr, rq.coords, rq.vals, kk)
         res["recall_prefill"]["recall_at_%d" % kk] = round(
             recall_vs_exact(ora, rq, g_ids.astype(np.int64), g_cnt, kk, O.max_threads()), 4)
+    if not args.no_cpu_baseline:
+        res["cpu_oracle"] = oracle_qps(ora, gen.serving_queries(10, 512), 100, O.max_threads())
+        res["cpu_oracle"]["sample"] = "512 queries of the serving law on the prefilled index, k = 100"
+        log("serving oracle %.1f q/s (512 queries)" % res["cpu_oracle"]["qps"])
     del ora
     log("serving recall on the prefilled index (64 queries): %s" % res["recall_prefill"])
 
@@ -932,6 +955,11 @@ def small_learned(args, dev, P, gen, np, torch):
     for name in ("plain", "batched", "learned"):
         res[name]["recall_at_10"] = rec
     log("small recall@10 %.4f (%d queries)" % (rec, nq))
+    if not args.no_cpu_baseline:
+        res["cpu_oracle"] = {"small_100_queries": oracle_qps(ora, w.queries, 10, O.max_threads()),
+                             "eval_queries": oracle_qps(ora, eq, 10, O.max_threads())}
+        log("small oracle %.1f q/s (100 queries), %.1f q/s (%d evaluation queries)" % (
+            res["cpu_oracle"]["small_100_queries"]["qps"], res["cpu_oracle"]["eval_queries"]["qps"], nq))
     return res
 
 

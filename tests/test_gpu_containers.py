@@ -160,6 +160,68 @@ def test_stale_blocks_give_the_bits_of_a_fresh_compaction():
     ix.close()
 
 
+def test_stale_blocks_h2_bf16_signed():
+    """The same equality with h = 2 mappings, bfloat16 sketches and signed
+    values: the bounds stored in the array containers (the h-fold minimum of
+    U and maximum of L, as bfloat16) and those the bitmap reading gathers
+    from the sketch are the same values, so a mutated index equals its
+    recompaction bit for bit, in the schedules h = 2 allows; and the
+    bfloat16 oracle's top-k of the live set."""
+    P = _lib()
+    rng = np.random.default_rng(31)
+    n, m, h, seed = 2000, 24, 2, 33
+    docs = gen.sparse_rows(32, 15_384, n, 1.1, rng.integers(20, 61, 15_384), "normal")
+    pool = gen.sparse_rows(34, 4000, n, 1.1, rng.integers(20, 61, 4000), "normal")
+    qs = gen.sparse_rows(35, 20, n, 1.1, np.full(20, 25), "normal")
+    ix = P.Index(n, m, h, capacity=docs.rows, hash_seed=seed, sketch_bf16=True)
+    P.load_docs(ix, docs)
+    cls = ix.container_classes()
+    assert cls[qs.coords].any()
+    live = {i: docs.row(i) for i in range(docs.rows)}
+    dels = rng.choice(sorted(live), 1500, replace=False).astype(np.uint32)
+    ix.delete_batch(dels)
+    for d in dels:
+        del live[int(d)]
+    nxt = 0
+    for ids in (np.arange(1200, dtype=np.uint32) + 100_000, dels[:200]):  # fresh slots, then freed ones
+        sub = pool.take(range(nxt, nxt + len(ids)))
+        ix.insert_batch(ids, sub.indptr, sub.coords, sub.vals)
+        for i, r in zip(ids, range(nxt, nxt + len(ids))):
+            live[int(i)] = pool.row(r)
+        nxt += len(ids)
+    t = _dev(qs)
+    saved = ix.schedule()
+
+    def every(what):
+        ref = None
+        for R in (16, 32, 64):
+            for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
+                ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=2048, persistent=True, qgroup=1)
+                got = _run(ix, t, 30, mode)
+                if ref is None:
+                    ref = got
+                for a, b in zip(ref, got):
+                    assert np.array_equal(a, b), (what, R, mode)
+        return ref
+
+    stale = every("stale")
+    ix.compact(classes=cls)
+    fresh = every("recompacted")
+    ix.set_schedule(saved["R_plain"], saved["R_batch"], saved["grid"], bool(saved["persistent"]), saved["qgroup"])
+    for a, b in zip(stale, fresh):
+        assert np.array_equal(a, b)
+    lid = np.array(sorted(live), dtype=np.uint32)
+    rows = [live[int(i)] for i in lid]
+    lens = np.array([len(c) for c, _ in rows], dtype=np.int64)
+    ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=ptr[1:])
+    docs_live = gen.CSR(ptr, np.concatenate([c for c, _ in rows]).astype(np.uint32),
+                        np.concatenate([v for _, v in rows]).astype(np.float32))
+    ora = O.Index(docs_live, n, m, h, seed, ids=lid, bf16=True)
+    parity.check_batch(fresh[0].astype(np.uint32), fresh[1], fresh[2], ora, qs, 30, what="h2 bf16 after mutations")
+    ix.close()
+
+
 def test_every_coordinate_an_array_long_segments():
     """Classes pinned to arrays for every coordinate: the Zipf head
     coordinates hold hundreds of postings per block, so their segments take
