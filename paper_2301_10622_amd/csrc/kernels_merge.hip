@@ -110,11 +110,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
     if (tid == 0) goff[G] = M;
   }
   __syncthreads();
-  // Every key of the query. Small groups (fewer than 64 keys on average): the
-  // threads stride over the concatenated keys and find each key's group by
-  // binary search in goff, so no lane idles on a short group; otherwise wave w
-  // walks groups w, w + 8, ..., its lanes the group's keys.
-  const bool flat = scan && M < 64u * G;
+  // Every key of the query. Small groups (fewer than 64 keys on average), or
+  // fewer groups than twice the waves (one long group: the k' exact scores of
+  // a re-rank): the threads stride over the concatenated keys and find each
+  // key's group by binary search in goff, so no lane or wave idles; otherwise
+  // wave w walks groups w, w + 8, ..., its lanes the group's keys.
+  const bool flat = scan && (M < 64u * G || G < 2u * kSelWaves);
   // At most kSelCache keys per thread: read them (and their groups) once into
   // registers and serve every pass from there.
   const bool cached = flat && M <= (uint32_t)(kSelCache * kSelBlock);
@@ -341,7 +342,10 @@ hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
     hipLaunchKernelGGL((k_select<false, true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
   else if (!sorted && pay)
     hipLaunchKernelGGL((k_select<true, false, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else return hipErrorInvalidValue;  // the two forms the search uses
+  else if (a.kmax > 512)  // unsorted without slots: the sampled pass's threshold
+    hipLaunchKernelGGL((k_select<false, false, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_select<false, false, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -833,13 +833,13 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
     m1.set_fallback = false;
     m1.q0 = 0;
     m1.nqm = p.nq;
-    if (p.k_s <= kMaxK) {  // sorted, into the sample buffers
+    if (p.k_s <= kMaxK) {  // into the sample buffers, unsorted: only their lowest score is used
       m1.res_ids = w.ss_ids;
       m1.res_scores = w.ss_sc;
       m1.res_cnt = w.ss_cnt;
       m1.res_slots = nullptr;
       m1.slots = false;
-      m1.sorted = true;
+      m1.sorted = false;
     }  // else (re-rank with a very wide k'): unsorted, into the re-rank buffers
     st = enqueue_merge(w, m1, s);
     if (st != SNN_OK) return st;

@@ -52,7 +52,7 @@ struct SearchWs {
   uint32_t *qlist = nullptr, *nlist = nullptr;  // learned filter: the queries that fall back
   uint32_t *nz_full = nullptr;                  // [nq] whole non-zero count of each prepared query
   uint32_t *sthr = nullptr;                     // [nq] starting thresholds from a sample of the tiles
-  uint32_t *ss_ids = nullptr, *ss_cnt = nullptr;  // the sample pass's sorted selection (k_s <= 4,096)
+  uint32_t *ss_ids = nullptr, *ss_cnt = nullptr;  // the sample pass's selection (k_s <= 4,096), unsorted
   float *ss_sc = nullptr;
   uint32_t *cslot = nullptr;  // re-rank: slot of each candidate
   uint32_t *rr_ids = nullptr, *rr_slot = nullptr, *rr_cnt = nullptr;  // re-rank: the k' selected candidates
