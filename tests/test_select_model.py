@@ -4,8 +4,10 @@ against a brute-force sort, and of a variant that starts below the leading
 bits every valid key shares (found from the largest and the smallest valid
 key): both find the k-th largest key on random key sets with invalid (zero)
 keys, ties, one sign only (the keys of non-negative scores all carry the top
-bit) and mixed signs. Only the order-preserving key map of snn_device.h is
-shared with the library; the walk is restated here."""
+bit) and mixed signs. Also the merge select's walk over 64-bit (score, id) keys in
+12-bit digits, from the top bit and from below the prefix all keys share.
+Only the order-preserving key map of snn_device.h is shared with the library;
+the walks are restated here."""
 import numpy as np
 import pytest
 
@@ -86,3 +88,56 @@ def test_radix_select_model_against_a_sort(law):
             continue
         k = int(rng.integers(1, nv))  # the select runs when more than k keys are valid
         check(keys, k)
+
+
+def digit_walk(keys, keep, start_at_prefix):
+    """The merge select's walk over 64-bit keys, 12-bit digits at a time (a
+    histogram of the next digit of the keys that share the prefix found so
+    far, then the bin holding the need-th largest key), optionally started
+    below the leading bits the largest and the smallest key share. Returns
+    the threshold T: the result is every key >= T."""
+    P, pb, need = 0, 0, keep
+    if start_at_prefix:
+        diff = int(keys.max()) ^ int(keys.min())
+        if diff:
+            pb = 64 - diff.bit_length()
+            P = int(keys.max()) >> (64 - pb) if pb else 0
+    while True:
+        d = min(12, 64 - pb)
+        sel = keys if pb == 0 else keys[(keys >> np.uint64(64 - pb)) == np.uint64(P)]
+        digit = (sel >> np.uint64(64 - pb - d)) & np.uint64((1 << d) - 1)
+        hist = np.bincount(digit.astype(np.int64), minlength=1 << d)
+        above = 0
+        for b in range((1 << d) - 1, -1, -1):
+            if above < need <= above + hist[b]:
+                break
+            above += hist[b]
+        in_bin, need = int(hist[b]), need - above
+        P, pb = (P << d) | b, pb + d
+        if in_bin == need or pb == 64:
+            return P if pb == 64 else P << (64 - pb)
+
+
+@pytest.mark.parametrize("law", ["exp", "narrow", "ties"])
+def test_merge_select_digit_walk_against_a_sort(law):
+    """The 64-bit digit walk of the merge select, from the top bit and from
+    below the shared prefix, returns a threshold that exactly `keep` keys
+    reach, the keep-th largest key, on distinct (score, id) keys whose scores
+    share many leading bits (the candidates of a thresholded pass)."""
+    rng = np.random.default_rng({"exp": 21, "narrow": 22, "ties": 23}[law])
+    for trial in range(200):
+        n = int(rng.integers(2, 3000))
+        if law == "exp":
+            s = 5.0 + rng.exponential(1.0, n)
+        elif law == "narrow":
+            s = 7.0 + rng.integers(0, 200, n) * 2.0 ** -18
+        else:
+            s = rng.integers(1, 4, n).astype(np.float64)
+        ids = rng.choice(1 << 31, n, replace=False).astype(np.uint64)
+        keys = (ord_key(s.astype(np.float32)) << np.uint64(32)) | (np.uint64(0xFFFFFFFF) - ids)
+        keep = int(rng.integers(1, n)) if n > 1 else 1
+        want = np.sort(keys)[::-1][keep - 1]
+        for skip in (False, True):
+            T = digit_walk(keys, keep, skip)
+            assert np.count_nonzero(keys >= np.uint64(T)) == keep, (trial, skip)
+            assert np.uint64(T) <= want
