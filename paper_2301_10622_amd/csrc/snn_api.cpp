@@ -935,6 +935,11 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   const uint32_t tile_docs = (uint32_t)kBlock * p.R;
   p.tiles = (next_fresh + tile_docs - 1) / tile_docs;
   if (p.tiles == 0) return SNN_OK;
+  // A batch with no more (query group, tile) items than the persistent grid
+  // has workgroups gains nothing from the work queues (each workgroup would
+  // take at most one item), and the emptied queues would still cost every
+  // workgroup a round of atomics on them: it runs one workgroup per item.
+  if (p.persistent && (uint64_t)((nq + p.qgroup - 1) / p.qgroup) * p.tiles <= p.grid) p.persistent = false;
   p.kt = std::min<uint32_t>(k, tile_docs);
   // A wide k (k' of Alg. 7 when re-ranking; a sixteenth of a tile or more): a
   // tile's own selection keeps the tile's k best, a large share of it (all of
