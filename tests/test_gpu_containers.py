@@ -45,7 +45,8 @@ def _every_schedule(ix, t, k, what):
     ref = None
     try:
         for R, Q in SCHEDULES:
-            for persistent, grid in ((True, 2048), (False, 2048)):
+            # persistent on a 64-workgroup grid (fewer workgroups than items)
+            for persistent, grid in ((True, 64), (False, 2048)):
                 ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=grid, persistent=persistent, qgroup=Q)
                 for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
                     if mode == P.MODE_PLAIN and not persistent:
@@ -196,7 +197,7 @@ def test_stale_blocks_h2_bf16_signed():
         ref = None
         for R in (16, 32, 64):
             for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
-                ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=2048, persistent=True, qgroup=1)
+                ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=64, persistent=True, qgroup=1)
                 got = _run(ix, t, 30, mode)
                 if ref is None:
                     ref = got
@@ -278,7 +279,7 @@ def test_arrays_with_other_sketches(variant):
     shapes = SCHEDULES if h == 1 else ((16, 1), (32, 1), (64, 1))
     for R, Q in shapes:
         for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
-            ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=2048, persistent=True, qgroup=Q)
+            ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=64, persistent=True, qgroup=Q)
             got = _run(ix, t, 30, mode)
             if ref is None:
                 ref = got

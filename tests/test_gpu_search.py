@@ -397,7 +397,9 @@ def test_all_schedules_give_identical_results(small):
     saved = ix.schedule()
     try:
         for R, Q in ((16, 1), (32, 1), (64, 1), (16, 2), (16, 3), (8, 2), (8, 4)):
-            for persistent, grid in ((True, 1024), (True, 4096), (False, 2048)):
+            # a 64-workgroup persistent grid: these batches have more items than
+            # that (a larger grid would run them one workgroup per item)
+            for persistent, grid in ((True, 64), (True, 1024), (False, 2048)):
                 ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=grid, persistent=persistent, qgroup=Q)
                 for mode in (P.MODE_PLAIN, P.MODE_BATCHED):
                     for k in (10, 100):

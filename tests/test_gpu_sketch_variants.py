@@ -129,7 +129,7 @@ def test_sketch_variants_every_schedule_same_bits(bf16, upper):
     ref = ix.search_ex(qs.indptr, qs.coords, qs.vals, 10, mode=P.MODE_PLAIN)
     for R, Q in ((16, 1), (32, 1), (64, 1), (16, 2), (16, 3), (8, 2), (8, 4)):
         for persistent in (True, False):
-            ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=2048, persistent=persistent, qgroup=Q)
+            ix.set_schedule(R_plain=max(R, 16), R_batch=R, grid=64 if persistent else 2048, persistent=persistent, qgroup=Q)
             got = ix.search_ex(qs.indptr, qs.coords, qs.vals, 10, mode=P.MODE_BATCHED)
             for a, b in zip(ref, got):
                 assert np.array_equal(a, b), (R, Q, persistent)
