@@ -139,10 +139,11 @@ hipError_t launch_rerank(const RerankArgs &a, uint32_t nq, hipStream_t s) {
     return hipErrorInvalidValue;
   const size_t lds = (size_t)a.hash_cap * 8;
   // workgroups per query: enough to fill the device for small batches, and at
-  // least 512 candidates each
+  // least 128 candidates each (one query of k' = 1,000: 7 workgroups; of
+  // k' = 20,000: 156)
   const uint32_t by_grid = std::max<uint32_t>(1u, 1024u / nq);
-  const uint32_t by_work = std::max<uint32_t>(1u, a.kprime / 512u);
-  const uint32_t splits = std::min<uint32_t>(64u, std::min(by_grid, by_work));
+  const uint32_t by_work = std::max<uint32_t>(1u, a.kprime / 128u);
+  const uint32_t splits = std::min<uint32_t>(256u, std::min(by_grid, by_work));
   for (uint32_t c0 = 0; c0 < nq; c0 += 65535u) {
     RerankArgs b = a;
     b.q0 = a.q0 + c0;
