@@ -28,11 +28,10 @@ __device__ __forceinline__ cptr<T> as_const(const T *p) {
 // written in order; otherwise (the k' candidates of the re-rank, up to 65,536)
 // they are written in the order found, with their slots.
 // ---------------------------------------------------------------------------
-constexpr int kSelBlock = 512;
-constexpr int kSelWaves = kSelBlock / 64;
+constexpr int kSelBlock = 512;  // threads of a select workgroup (1,024 for small batches)
 constexpr int kSelBins = 4096;
 constexpr uint32_t kSelScanMax = 2048;  // groups whose key offsets fit in LDS
-constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 per query)
+constexpr int kSelCache = 8;             // keys per thread held in registers (4,096 or 8,192 per query)
 constexpr int kSelU = 4;                 // keys of a group per lane in flight (large groups)
 // keys copied to LDS after the first radix pass: 1,024, or 4,096 in the form
 // launched for a sorted top-k with k above 512 (more LDS, one workgroup per CU)
@@ -40,8 +39,9 @@ template <bool kBig>
 constexpr uint32_t sel_cmp() { return kBig ? 4096u : 1024u; }
 
 // Inclusive prefix sum of v over the workgroup's threads, and the total: a
-// shuffle scan inside each wave, then the 8 wave totals through LDS (two
+// shuffle scan inside each wave, then the kW wave totals through LDS (two
 // barriers, where a scan over the threads in LDS takes two per doubling).
+template <int kW>
 __device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t x = v;
@@ -54,7 +54,7 @@ __device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t *wsum, uint32_
   __syncthreads();
   uint32_t off = 0, t = 0;
 #pragma unroll
-  for (int w = 0; w < kSelWaves; ++w) {
+  for (int w = 0; w < kW; ++w) {
     const uint32_t sw = wsum[w];
     off += w < wave ? sw : 0u;
     t += sw;
@@ -64,11 +64,12 @@ __device__ __forceinline__ uint32_t sel_scan(uint32_t v, uint32_t *wsum, uint32_
   return x + off;
 }
 
-template <bool kPay, bool kSorted, bool kBig>
-__global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
+template <bool kPay, bool kSorted, bool kBig, int kB>
+__global__ __launch_bounds__(kB) void k_select(SelectArgs a) {
+  constexpr int kWv = kB / 64;  // waves of the workgroup
   constexpr uint32_t kSelCmp = sel_cmp<kBig>();
   __shared__ uint32_t hist[kSelBins];
-  __shared__ uint32_t wsum[kSelWaves];
+  __shared__ uint32_t wsum[kWv];
   __shared__ uint64_t sel[kSorted ? kMaxK : 1];
   __shared__ uint32_t sels[kPay && kSorted ? kMaxK : 1];
   __shared__ uint32_t sh_bin, sh_need, sh_pos;
@@ -92,15 +93,15 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   // group's first key in the concatenation of all groups (thread t sums the
   // groups t * per .. t * per + per - 1, then a scan over the threads)
   const bool scan = G <= kSelScanMax;
-  const uint32_t gper = (G + kSelBlock - 1) / kSelBlock;
+  const uint32_t gper = (G + kB - 1) / kB;
   uint32_t mine = 0;
   if (scan) {
     for (uint32_t g = (uint32_t)tid * gper; g < min(G, ((uint32_t)tid + 1) * gper); ++g) mine += cnts[g];
   } else {
-    for (uint32_t g = (uint32_t)tid; g < G; g += kSelBlock) mine += cnts[g];
+    for (uint32_t g = (uint32_t)tid; g < G; g += kB) mine += cnts[g];
   }
   uint32_t M;
-  const uint32_t incl = sel_scan(mine, wsum, M);
+  const uint32_t incl = sel_scan<kWv>(mine, wsum, M);
   if (scan) {
     uint32_t o = incl - mine;
     for (uint32_t g = (uint32_t)tid * gper; g < min(G, ((uint32_t)tid + 1) * gper); ++g) {
@@ -115,16 +116,16 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   // a re-rank): the threads stride over the concatenated keys and find each
   // key's group by binary search in goff, so no lane or wave idles; otherwise
   // wave w walks groups w, w + 8, ..., its lanes the group's keys.
-  const bool flat = scan && (M < 64u * G || G < 2u * kSelWaves);
+  const bool flat = scan && (M < 64u * G || G < 2u * kWv);
   // At most kSelCache keys per thread: read them (and their groups) once into
   // registers and serve every pass from there.
-  const bool cached = flat && M <= (uint32_t)(kSelCache * kSelBlock);
+  const bool cached = flat && M <= (uint32_t)(kSelCache * kB);
   uint64_t ck[kSelCache];
   uint32_t cg[kSelCache], ce[kSelCache];
   if (cached) {
 #pragma unroll
     for (int u = 0; u < kSelCache; ++u) {
-      const uint32_t i = (uint32_t)tid + (uint32_t)u * kSelBlock;
+      const uint32_t i = (uint32_t)tid + (uint32_t)u * kB;
       ck[u] = 0;
       cg[u] = ce[u] = 0;
       if (i < M) {
@@ -144,19 +145,19 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   auto for_each = [&](auto f) {
     if (compacted) {
       const uint32_t n = cmp_n;
-      for (uint32_t i = (uint32_t)tid; i < n; i += kSelBlock) f(cmp_key[i], cmp_g[i], cmp_e[i]);
+      for (uint32_t i = (uint32_t)tid; i < n; i += kB) f(cmp_key[i], cmp_g[i], cmp_e[i]);
     } else if (cached) {
 #pragma unroll
       for (int u = 0; u < kSelCache; ++u)
-        if ((uint32_t)tid + (uint32_t)u * kSelBlock < M) f(ck[u], cg[u], ce[u]);
+        if ((uint32_t)tid + (uint32_t)u * kB < M) f(ck[u], cg[u], ce[u]);
     } else if (flat) {
       constexpr int U = 4;  // keys in flight per thread
-      for (uint32_t i0 = (uint32_t)tid; i0 < M; i0 += U * kSelBlock) {
+      for (uint32_t i0 = (uint32_t)tid; i0 < M; i0 += U * kB) {
         uint64_t kk[U];
         uint32_t gg[U], ee[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const uint32_t i = i0 + (uint32_t)u * kSelBlock;
+          const uint32_t i = i0 + (uint32_t)u * kB;
           gg[u] = ee[u] = 0;
           kk[u] = 0;
           if (i < M) {
@@ -173,13 +174,13 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (i0 + (uint32_t)u * kSelBlock < M) f(kk[u], gg[u], ee[u]);
+          if (i0 + (uint32_t)u * kB < M) f(kk[u], gg[u], ee[u]);
       }
     } else {
       // two groups at a time and kSelU keys of each per lane, so 2 kSelU
       // loads are in flight per lane
-      for (uint32_t g = (uint32_t)wave; g < G; g += 2 * kSelWaves) {
-        const uint32_t g2 = g + kSelWaves;
+      for (uint32_t g = (uint32_t)wave; g < G; g += 2 * kWv) {
+        const uint32_t g2 = g + kWv;
         const uint32_t c1 = scan ? goff[g + 1] - goff[g] : cnts[g];
         const uint32_t c2 = g2 < G ? (scan ? goff[g2 + 1] - goff[g2] : cnts[g2]) : 0u;
         const uint64_t *s1 = base + (size_t)g * a.in_stride;
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
     for (;;) {
       const int d = min(12, 64 - pb);
       const uint32_t nb = 1u << d;
-      for (uint32_t i = tid; i < nb; i += kSelBlock) hist[i] = 0u;
+      for (uint32_t i = tid; i < nb; i += kB) hist[i] = 0u;
       __syncthreads();
       for_each([&](uint64_t key, uint32_t, uint32_t) {
         if (pb == 0 || (key >> (64 - pb)) == P)
@@ -221,12 +222,12 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       __syncthreads();
       // counts above each thread's 8 bins (suffix scan), then the bin that
       // holds the need-th largest key
-      const uint32_t per = (nb + kSelBlock - 1) / kSelBlock;
+      const uint32_t per = (nb + kB - 1) / kB;
       const uint32_t b0 = (uint32_t)tid * per;
       uint32_t s = 0;
       for (uint32_t b = b0; b < b0 + per && b < nb; ++b) s += hist[b];
       uint32_t tot;
-      const uint32_t pre = sel_scan(s, wsum, tot);
+      const uint32_t pre = sel_scan<kWv>(s, wsum, tot);
       uint32_t above = tot - pre;  // keys in the bins of the threads after this one
       for (int b = (int)min(b0 + per, nb) - 1; b >= (int)b0; --b) {
         const uint32_t h = hist[b];
@@ -298,11 +299,11 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   }
   uint32_t np = 1;
   while (np < keep) np <<= 1;
-  for (uint32_t i = keep + tid; i < np; i += kSelBlock) sel[i] = 0ull;
+  for (uint32_t i = keep + tid; i < np; i += kB) sel[i] = 0ull;
   for (uint32_t size = 2; size <= np; size <<= 1)
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
       __syncthreads();
-      for (uint32_t i = tid; i < (np >> 1); i += kSelBlock) {
+      for (uint32_t i = tid; i < (np >> 1); i += kB) {
         const uint32_t lo = 2 * stride * (i / stride) + (i % stride);
         const uint32_t hi = lo + stride;
         const bool down = (lo & size) == 0;
@@ -319,7 +320,7 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
       }
     }
   __syncthreads();
-  for (uint32_t r = tid; r < keep; r += kSelBlock) {
+  for (uint32_t r = tid; r < keep; r += kB) {
     const uint64_t key = sel[r];
     ids[r] = 0xFFFFFFFFu - (uint32_t)key;
     sc[r] = key_value((uint32_t)(key >> 32));
@@ -331,21 +332,29 @@ __global__ __launch_bounds__(kSelBlock) void k_select(SelectArgs a) {
   }
 }
 
+template <int kB>
+static void launch_select_b(const SelectArgs &a, bool sorted, bool pay, hipStream_t s) {
+  if (sorted && !pay && a.kmax > 512)
+    hipLaunchKernelGGL((k_select<false, true, true, kB>), dim3(1, a.nq), dim3(kB), 0, s, a);
+  else if (sorted && !pay)
+    hipLaunchKernelGGL((k_select<false, true, false, kB>), dim3(1, a.nq), dim3(kB), 0, s, a);
+  else if (!sorted && pay)
+    hipLaunchKernelGGL((k_select<true, false, false, kB>), dim3(1, a.nq), dim3(kB), 0, s, a);
+  else if (a.kmax > 512)  // unsorted without slots: the sampled pass's threshold
+    hipLaunchKernelGGL((k_select<false, false, true, kB>), dim3(1, a.nq), dim3(kB), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_select<false, false, false, kB>), dim3(1, a.nq), dim3(kB), 0, s, a);
+}
+
 hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
   if (a.kmax == 0 || a.in_stride == 0 || !a.res_ids || !a.res_scores || !a.res_cnt) return hipErrorInvalidValue;
   if (sorted ? a.kmax > kMaxK : a.kmax > kMaxKPrime) return hipErrorInvalidValue;
   const bool pay = a.in_slot != nullptr;
   if (pay != (a.res_slots != nullptr)) return hipErrorInvalidValue;
-  if (sorted && !pay && a.kmax > 512)
-    hipLaunchKernelGGL((k_select<false, true, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else if (sorted && !pay)
-    hipLaunchKernelGGL((k_select<false, true, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else if (!sorted && pay)
-    hipLaunchKernelGGL((k_select<true, false, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else if (a.kmax > 512)  // unsorted without slots: the sampled pass's threshold
-    hipLaunchKernelGGL((k_select<false, false, true>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_select<false, false, false>), dim3(1, a.nq), dim3(kSelBlock), 0, s, a);
+  // a small batch (fewer queries than half the CUs) gets 1,024-thread
+  // workgroups: one workgroup per query works alone on its CU
+  if (a.nq < 128) launch_select_b<1024>(a, sorted, pay, s);
+  else launch_select_b<kSelBlock>(a, sorted, pay, s);
   return hipGetLastError();
 }
 
