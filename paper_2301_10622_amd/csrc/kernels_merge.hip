@@ -351,9 +351,9 @@ hipError_t launch_select(const SelectArgs &a, bool sorted, hipStream_t s) {
   if (sorted ? a.kmax > kMaxK : a.kmax > kMaxKPrime) return hipErrorInvalidValue;
   const bool pay = a.in_slot != nullptr;
   if (pay != (a.res_slots != nullptr)) return hipErrorInvalidValue;
-  // a small batch (fewer queries than half the CUs) gets 1,024-thread
-  // workgroups: one workgroup per query works alone on its CU
-  if (a.nq < 128) launch_select_b<1024>(a, sorted, pay, s);
+  // a batch of at most as many queries as CUs gets 1,024-thread workgroups:
+  // one workgroup per query works alone on its CU
+  if (a.nq <= 256) launch_select_b<1024>(a, sorted, pay, s);
   else launch_select_b<kSelBlock>(a, sorted, pay, s);
   return hipGetLastError();
 }
