@@ -1039,10 +1039,13 @@ snn_status snn_index::run_search(uint32_t nq, const uint64_t *d_ptr, uint64_t to
 }
 
 // LDS hash slots the re-rank kernel needs for queries of at most `max_nnz`
-// entries: a power of two at least twice that (a table at most half full).
+// entries: a power of two at least 8 times that (a table at most 1/8 full, so
+// probes nearly always end in the first bucket) up to 4,096 slots (32 KB, three
+// workgroups per CU), else at least twice that (at most half full).
 static uint32_t rerank_hash_cap(uint64_t max_nnz) {
   uint64_t ub = std::min<uint64_t>(max_nnz, (uint64_t)kPrepCap);
   uint32_t cap = 64;
+  while (cap < 8 * ub && cap < 4096) cap <<= 1;
   while (cap < 2 * ub) cap <<= 1;
   return cap;
 }

@@ -140,6 +140,40 @@ def test_rerank_after_deletes_and_reinserts():
     assert full >= 0.85 * qs.rows
 
 
+def _remap(csr, f):
+    """The same vectors over another dimensionality: coordinate c becomes f(c),
+    rows kept in ascending coordinate order."""
+    c = f(csr.coords.astype(np.int64))
+    coords = np.empty(len(c), dtype=np.uint32)
+    vals = np.empty_like(csr.vals)
+    for r in range(csr.rows):
+        a, b = int(csr.indptr[r]), int(csr.indptr[r + 1])
+        o = np.argsort(c[a:b], kind="stable")
+        coords[a:b] = c[a:b][o]
+        vals[a:b] = csr.vals[a:b][o]
+    return gen.CSR(csr.indptr.copy(), coords, vals)
+
+
+@pytest.mark.parametrize("dim,f", [(65536, lambda c: 65535 - 65 * c), (131072, lambda c: 131071 - 65 * c)],
+                         ids=["narrow-65536", "wide-131072"])
+def test_rerank_forward_store_coordinate_widths(dim, f):
+    """Coordinates at the top of the 16-bit range (dimensionality 65,536, the
+    largest coordinate 65,535) and all above it (131,072), where any 16-bit
+    truncation in the forward store or the query's table would alias them."""
+    P = _lib()
+    w = gen.make_small(4, docs=4000, queries=30)
+    docs, qs = _remap(w.docs, f), _remap(w.queries, f)
+    assert int(docs.coords.max()) == dim - 1
+    assert int(docs.coords.min()) > (0 if dim == 65536 else 65535)
+    ix = P.Index(dim, w.m, w.h, capacity=docs.rows, hash_seed=w.hash_seed, forward_store=True)
+    P.load_docs(ix, docs)
+    ora = O.Index(docs, dim, w.m, w.h, w.hash_seed)
+    ids, sc, cnt = ix.search_rerank(qs.indptr, qs.coords, qs.vals, 10, 500)
+    full = _check(ids, sc, cnt, ora, qs, 10, 500, "dim %d" % dim)
+    assert full >= 0.85 * qs.rows, full
+    ix.close()
+
+
 def test_rerank_kprime_above_tile_and_collection():
     """k' larger than a tile (4,096 slots) and than the collection: every tile
     passes all its documents on, and with k' >= live the result is the exact
