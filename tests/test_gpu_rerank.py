@@ -174,6 +174,28 @@ def test_rerank_forward_store_coordinate_widths(dim, f):
     ix.close()
 
 
+@pytest.mark.parametrize("lo,hi,fixed", [(500, 700, 12), (1500, 2048, 12), (3900, 4096, 10)],
+                         ids=["q500", "q2000", "q4096"])
+def test_rerank_long_queries(lo, hi, fixed):
+    """Queries of 500 to 4,096 (the most a query may hold) non-zeros. The
+    query's LDS table is at most 1/8 full up to 512 of them and up to half
+    full beyond, where probes often walk on past full buckets."""
+    P = _lib()
+    rng = np.random.default_rng(17)
+    dim = 8192
+    docs = gen.sparse_rows(51, 6000, dim, 0.3, rng.integers(20, 400, 6000), "normal")
+    qs = gen.sparse_rows(52, 12, dim, 0.3, rng.integers(lo, hi + 1, 12), "normal")
+    ix = P.Index(dim, 32, 1, capacity=docs.rows, hash_seed=3, forward_store=True)
+    P.load_docs(ix, docs)
+    ora = O.Index(docs, dim, 32, 1, 3)
+    ids, sc, cnt = ix.search_rerank(qs.indptr, qs.coords, qs.vals, 10, 300)
+    full = _check(ids, sc, cnt, ora, qs, 10, 300, "nnz %d..%d" % (lo, hi))
+    # queries whose k'-th estimate is separated from the next, from the
+    # oracle's scores alone: checked in full, the others by the open-edge rule
+    assert full == fixed, full
+    ix.close()
+
+
 def test_rerank_kprime_above_tile_and_collection():
     """k' larger than a tile (4,096 slots) and than the collection: every tile
     passes all its documents on, and with k' >= live the result is the exact
