@@ -817,9 +817,16 @@ snn_status snn_index::enqueue_search(const SearchPlan &p, const SearchOpts &o, h
   } else if (p.tiles_s) {
     HIP_TRY(this, launch_fill_u32(w.thr, 0u, p.nq, s), "thr fill");
     // one k for every query here: a tile keeps at most kmax candidates per
-    // query (the stride of this pass), whatever the query's own k
+    // query (the stride of this pass), whatever the query's own k. That is
+    // four times a sampled tile's share of the k_s best (at least 32), not
+    // k_s: the lowest of the k_s best of what the tiles keep is the sample's
+    // own k_s-th best unless one tile held more of them than that, and then it
+    // is lower, which only lets more documents through the main pass (what the
+    // tiles keep is a subset of the sample; with fewer than k_s of them there
+    // is no threshold). The tile selects and the sample's select get cheaper.
     a.tiles = p.tiles_s;
-    a.kmax = std::min(p.k_s, p.kt);
+    const uint32_t share = (uint32_t)std::max<uint64_t>(32u, (4ull * p.k_s + p.tiles_s - 1) / p.tiles_s);
+    a.kmax = std::min(std::min(p.k_s, p.kt), share);
     a.kq = nullptr;
     a.nselect = nullptr;
     st = tiles_pass(nullptr, nullptr);
