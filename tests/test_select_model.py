@@ -5,8 +5,9 @@ bits every valid key shares (found from the largest and the smallest valid
 key): both find the k-th largest key on random key sets with invalid (zero)
 keys, ties, one sign only (the keys of non-negative scores all carry the top
 bit) and mixed signs. Also the merge select's walk over 64-bit (score, id) keys in
-12-bit digits, from the top bit and from below the prefix all keys share.
-Only the order-preserving key map of snn_device.h is shared with the library;
+12-bit digits, from the top bit and from below the prefix all keys share,
+and the wide-k first pass's starting threshold taken from a share of each
+sampled tile. Only the order-preserving key map of snn_device.h is shared with the library;
 the walks are restated here."""
 import numpy as np
 import pytest
@@ -141,3 +142,43 @@ def test_merge_select_digit_walk_against_a_sort(law):
             T = digit_walk(keys, keep, skip)
             assert np.count_nonzero(keys >= np.uint64(T)) == keep, (trial, skip)
             assert np.uint64(T) <= want
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sampled_threshold_from_a_share_of_each_tile(seed):
+    """The wide-k first pass lets each sampled tile keep only
+    max(32, 4 k_s / tiles_s) of its best keys, and takes the lowest of the k_s
+    best of what they keep as the starting threshold. What they keep is a
+    subset of the sample, so that threshold is never above the sample's own
+    k_s-th best (a lower threshold only lets more documents through); it equals
+    it unless one tile held more of the k_s best than it kept, and with fewer
+    than k_s kept in all there is no threshold. Checked on tiles of random
+    scores, on tiles whose first few hold all the largest scores, and on tiles
+    of few scores."""
+    rng = np.random.default_rng(seed)
+    tiles_s = int(rng.integers(4, 80))
+    tile = 4096
+    k = int(rng.integers(1000, 20001))
+    tiles = tiles_s * 16
+    k_s = (2 * k * tiles_s + tiles - 1) // tiles + 32
+    share = max(32, (4 * k_s + tiles_s - 1) // tiles_s)
+    keep = min(k_s, tile, share)
+    for layout in ("random", "skewed", "sparse"):
+        per = []
+        for t in range(tiles_s):
+            n = tile if layout != "sparse" else int(rng.integers(0, 64))
+            s = rng.standard_normal(n).astype(np.float32)
+            if layout == "skewed" and t < 2:
+                s += 8.0  # the first tiles hold every large score
+            per.append(np.sort(ord_key(s))[::-1])
+        sample = np.sort(np.concatenate(per))[::-1]
+        kept = np.sort(np.concatenate([p[:keep] for p in per]))[::-1]
+        thr_kept = int(kept[k_s - 1]) if len(kept) >= k_s else 0
+        thr_sample = int(sample[k_s - 1]) if len(sample) >= k_s else 0
+        assert thr_kept <= thr_sample
+        top = sample[:k_s]
+        crowded = any(int(np.count_nonzero(p >= top[-1])) > keep for p in per) if len(sample) >= k_s else False
+        if not crowded and len(kept) >= k_s:
+            assert thr_kept == thr_sample, layout
+        if layout == "random":
+            assert not crowded  # an even spread never fills four times a tile's share
