@@ -953,14 +953,17 @@ snn_status snn_index::plan_search(uint32_t nq, const uint64_t *d_ptr, uint64_t t
   // it when k reaches the tile), so a query hands the selection about
   // tiles x min(k, tile) candidates. A first pass over the first
   // tiles / kSampleStride tiles selects the k_s best there, k_s chosen so that
-  // about 2 k documents of the whole collection score at least the lowest of
-  // them (a slot range holds a random sample of the collection's documents;
-  // when it does not, more queries run the no-threshold pass, nothing else).
+  // about 1.5 k documents of the whole collection (plus 32 of the sample's
+  // documents' worth, a margin for small samples) score at least the lowest of
+  // them: k_s is a count of a random sample, whose relative spread is about
+  // 1 / sqrt(k_s), 2-9% here, so fewer than k pass only many spreads away (a
+  // slot range holds a random sample of the collection's documents; when it
+  // does not, more queries run the no-threshold pass, nothing else).
   // With per-query k the batch k sets k_s: a lower threshold is still valid.
   p.tiles_s = p.k_s = 0;
   if (mode == SNN_MODE_BATCHED && !o.thr_init && (uint64_t)k * 16 >= tile_docs && p.tiles >= 4 * kSampleStride) {
     const uint32_t ts = p.tiles / kSampleStride;
-    const uint64_t ks = (2ull * k * ts + p.tiles - 1) / p.tiles + 32;
+    const uint64_t ks = (3ull * k * ts + 2ull * p.tiles - 1) / (2ull * p.tiles) + 32;
     if (ks < k) {
       p.tiles_s = ts;
       p.k_s = (uint32_t)ks;

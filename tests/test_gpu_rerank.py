@@ -307,7 +307,7 @@ def _search_two_ways(ix, q, k, kp, c=0):
 def test_rerank_kprime_above_tile_starts_from_sampled_thresholds():
     """k' = 5,000 over 300,000 documents (74 tiles of 4,096): the first pass over
     4 sampled tiles gives each query a starting threshold, and the full pass
-    hands the selection about 2 k' candidates per query instead of every
+    hands the selection about 1.5 k' candidates per query instead of every
     document. Results: bit-identical to the search without it, and valid
     Alg. 7 results against the oracle."""
     w, d, ix, ora = _sampled_case(300_000, 8)

@@ -472,7 +472,7 @@ def test_wide_k_sampled_thresholds_bit_identical(wide, k):
     """k >= tile / 16 with 4,096-slot tiles starts each query from a threshold
     found on a sample of the tiles; with 16,384-slot tiles there are too few
     tiles to sample. Both must return the same bits, and the sampled search
-    must hand the selection a few k candidates per query (about 2 k plus the
+    must hand the selection a few k candidates per query (about 1.5 k plus the
     sample's margin of 32, scaled to the collection), not a share of every
     tile."""
     w, ix = wide

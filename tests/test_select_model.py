@@ -160,7 +160,7 @@ def test_sampled_threshold_from_a_share_of_each_tile(seed):
     tile = 4096
     k = int(rng.integers(1000, 20001))
     tiles = tiles_s * 16
-    k_s = (2 * k * tiles_s + tiles - 1) // tiles + 32
+    k_s = (3 * k * tiles_s + 2 * tiles - 1) // (2 * tiles) + 32
     share = max(32, (4 * k_s + tiles_s - 1) // tiles_s)
     keep = min(k_s, tile, share)
     for layout in ("random", "skewed", "sparse"):
