@@ -182,3 +182,31 @@ def test_sampled_threshold_from_a_share_of_each_tile(seed):
             assert thr_kept == thr_sample, layout
         if layout == "random":
             assert not crowded  # an even spread never fills four times a tile's share
+
+
+@pytest.mark.parametrize("tiles,k", [(74, 5000), (244, 1000), (244, 4096), (1221, 20000), (78, 20000)])
+def test_sampled_threshold_rarely_lets_fewer_than_k_through(tiles, k):
+    """The wide-k first pass takes the k_s-th best of the first tiles / 16
+    tiles, k_s = 1.5 k tiles_s / tiles + 32, as the starting threshold; a query
+    falls back (runs again with none) when fewer than k documents of the whole
+    collection reach it. On a collection in random slot order, the sample's
+    k_s-th best is the k_s-th largest of n_s uniform draws (a Beta order
+    statistic of the score distribution, whatever it is), and each of the other
+    documents reaches it with probability 1 minus that quantile. Over 200,000
+    draws of both, the documents that reach it sit at least 4.5 standard
+    deviations above k and none of the draws falls short: about 1.5 k pass,
+    so the fallback pass is for collections whose first slots are not a fair
+    sample."""
+    tile = 4096
+    ts = tiles // 16
+    n_s, n = ts * tile, tiles * tile
+    k_s = (3 * k * ts + 2 * tiles - 1) // (2 * tiles) + 32
+    rng = np.random.default_rng(tiles * 7 + k)
+    trials = 200_000
+    # the k_s-th largest of n_s uniforms is 1 - Beta(k_s, n_s - k_s + 1)
+    tail = rng.beta(k_s, n_s - k_s + 1, trials)
+    passing = k_s + rng.binomial(n - n_s, tail)
+    assert passing.min() >= k, (passing.min(), k)
+    z = (passing.mean() - k) / passing.std()
+    assert z >= 4.5, z
+    assert 1.4 * k <= passing.mean() <= 2.4 * k, passing.mean() / k
